@@ -1,0 +1,164 @@
+/*
+ * sld.h -- C ABI of the MI355X (gfx950) pressure Schur-complement library for the
+ * staggered semi-Lagrangian IMEX DG scheme of Tavelli & Boscheri (main triangles
+ * carry pressure, edge-based dual quads split into two sub-triangles carry velocity).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns sld_status (SLD_OK = 0); none throws, aborts or exits.
+ *   On failure sld_last_error() returns a thread-local message valid until the next
+ *   call on the same thread.
+ * - Degree p is 1..4.  N_phi = (p+1)(p+2)/2 main DOFs per triangle (Section 2.2),
+ *   N_psi = (p+1)^2 dual DOFs per edge (Section 2.2).
+ * - Main (pressure) vectors: float64 [ne][N_phi], row-major, triangle-major.  DOF k of
+ *   a triangle is the Lagrange node (a/p, b/p) of the reference triangle, numbered with
+ *   b outer and a inner, mapped by the affine map of eq. linmap (vertex 0 -> (0,0),
+ *   vertex 1 -> (1,0), vertex 2 -> (0,1)).
+ * - Dual (velocity) vectors: float64 [nd][2][N_psi]: edge-major, then component x/y,
+ *   then dual node (a/p, b/p) of the reference square numbered k = b*(p+1) + a
+ *   (Section 2.2).  Nodes with a+b <= p lie in the left sub-triangle (b_l, A, B) with
+ *   (1,0) -> A, (0,1) -> B; nodes with a+b > p lie in the right sub-triangle through
+ *   x = b_r + (1-b/p)(A-b_r) + (1-a/p)(B-b_r) (eq. mapDual).
+ * - Edge numbering (Section 2.1 leaves l and r arbitrary): edges are numbered in order of
+ *   first appearance scanning triangles i = 0.. and local edges alpha = 0,1,2, i.e. the
+ *   vertex pairs (v0,v1), (v1,v2), (v2,v0).  l(j) is the first triangle that references
+ *   edge j, A -> B follow l's counter-clockwise order, the unit normal n_j points from l
+ *   to r.  A boundary (wall) edge has r(j) = -1.
+ * - Device pointers are caller-owned (e.g. torch tensors' data_ptr()) and must hold the
+ *   stated number of float64 values on the handle's device.  The library keeps no caller
+ *   pointer after a call returns.  All device work is ordered on `stream` (a hipStream_t,
+ *   NULL = the default stream); functions return without waiting unless stated.
+ * - Handles are not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef SLD_H
+#define SLD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLD_OK = 0,
+    SLD_E_INVALID = 1,   /* bad argument: null pointer, degree out of range, bad size */
+    SLD_E_MESH = 2,      /* invalid mesh: non-positive area, non-manifold edge, ... */
+    SLD_E_NOMEM = 3,     /* device or host allocation failed */
+    SLD_E_HIP = 4,       /* a HIP runtime call failed */
+    SLD_E_NOCONV = 5,    /* CG reached maxit; the best iterate and report are written */
+    SLD_E_BREAKDOWN = 6, /* CG breakdown: d.Ad <= 0 or a non-finite scalar */
+    SLD_E_BUDGET = 7     /* a size or memory budget is exceeded */
+} sld_status;
+
+typedef struct sld_mesh_s* sld_mesh;
+typedef struct sld_disc_s* sld_disc;
+
+/* Thread-local message describing the last failure on this thread. */
+const char* sld_last_error(void);
+/* ABI version of this header (bumped on incompatible changes). */
+int32_t sld_abi_version(void);
+
+/* ------------------------------------------------------------------ mesh (Section 2.1)
+ * sld_mesh_create: build the staggered mesh from host arrays.
+ *   xy     host float64 [nv][2] vertex coordinates
+ *   tri    host int32 [ne][3] vertex ids, counter-clockwise (positive Jacobian, Section 2.4.1)
+ *   period host float64 [2] periodic box lengths, or NULL for a bounded domain.  For a
+ *          periodic box every triangle is unwrapped to the image of each vertex nearest
+ *          to its vertex 0, so triangles must be smaller than half a period.
+ *   device HIP device ordinal that will hold the geometry, or -1 for a host-only handle
+ *          (edge table and node queries only; device entry points then return
+ *          SLD_E_INVALID).
+ * Validation: ids in range, positive area, each vertex pair shared by at most two
+ * triangles with opposite orientation, no edge joining a triangle to itself
+ * (SLD_E_MESH otherwise).  Stores per triangle only its two edge vectors and its
+ * neighbour table on the device (the paper's point that only geometric quantities are
+ * stored per element, Section 2.4.1). */
+sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int64_t ne,
+                           const double* period, int32_t device, sld_mesh* out);
+sld_status sld_mesh_counts(sld_mesh mesh, int64_t* ne, int64_t* nd, int64_t* nv);
+/* Host copies of the edge table: left/right triangle, and the local edge index (0..2) of
+ * the edge in each; right = alpha_right = -1 on boundary edges.  Each array is [nd];
+ * any pointer may be NULL. */
+sld_status sld_mesh_edges(sld_mesh mesh, int32_t* left, int32_t* right,
+                          int32_t* alpha_left, int32_t* alpha_right);
+void sld_mesh_destroy(sld_mesh mesh);
+
+/* ------------------------------------------------------------------ discretisation
+ * sld_disc_create: reference operators of degree p (Section 2.4: mass matrices and the
+ * reference divergence/gradient operators, here in the equivalent form of reference
+ * stiffness, edge-node derivative and sub-triangle correction matrices), computed on the
+ * host in float64 by exact Gauss quadrature, plus the solver workspace on the device.
+ * The mesh must outlive the disc.  flags: reserved, pass 0. */
+sld_status sld_disc_create(sld_mesh mesh, int32_t p, uint32_t flags, sld_disc* out);
+sld_status sld_disc_info(sld_disc disc, int32_t* p, int32_t* nphi, int32_t* npsi);
+/* Host float64 [ne][N_phi][2] physical positions of the main DOF nodes (each triangle in
+ * its own unwrapped frame). */
+sld_status sld_main_nodes(sld_disc disc, double* xy_out);
+/* Host float64 [nd][N_psi][2] physical positions of the dual DOF nodes (in the frame of
+ * the edge's left triangle). */
+sld_status sld_dual_nodes(sld_disc disc, double* xy_out);
+/* Host float64 [ne][N_phi]: int_{T_i} phi_k dx (weights of the pressure gauge). */
+sld_status sld_main_weights(sld_disc disc, double* w_out);
+void sld_disc_destroy(sld_disc disc);
+
+/* ------------------------------------------------------------------ operators (device)
+ * sld_schur_apply: Kp = K p with K of eq. pressure_final,
+ *   (K p)_i = sum_{j in S_i} D_ij Mhat_j^{-1} (Q_{l(j),j} p_l + Q_{r(j),j} p_r),
+ * in the paper's sign (K is symmetric negative semi-definite; K 1 = 0).  Wall edges do
+ * not couple (K sums over interior edges).  p, Kp: device [ne][N_phi]; must not alias. */
+sld_status sld_schur_apply(sld_disc disc, const double* p, double* Kp, void* stream);
+/* sld_gradient: ghat_j = Mhat_j^{-1} (Q_{l(j),j} p_l + Q_{r(j),j} p_r) (eq. ad4.2, lambda = 1).
+ * p device [ne][N_phi] -> g device [nd][2][N_psi]; zero on wall edges. */
+sld_status sld_gradient(sld_disc disc, const double* p, double* g, void* stream);
+/* sld_divergence: (D v)_i = sum_{j in S_i} D_ij v_j (eq. D), interior edges only.
+ * v device [nd][2][N_psi] -> out device [ne][N_phi]. */
+sld_status sld_divergence(sld_disc disc, const double* v, double* out, void* stream);
+/* sld_pressure_rhs: b = scale * D v_star (right-hand side of eq. pressure_IMEX without the
+ * gravity and buoyancy sources; scale = 1/(a_ss dt)). */
+sld_status sld_pressure_rhs(sld_disc disc, const double* v_star, double scale, double* b,
+                            void* stream);
+/* sld_velocity_correct: v = v_star - coef * Mhat^{-1}(Q_l p_l + Q_r p_r) (eq. nc.2 solved for
+ * the new velocity after the pressure solve; coef = a_ss dt).  v may alias v_star. */
+sld_status sld_velocity_correct(sld_disc disc, const double* v_star, const double* p,
+                                double coef, double* v, void* stream);
+
+/* ------------------------------------------------------------------ CG (Section 2.3)
+ * sld_cg_solve: matrix-free conjugate gradients for K p = b (run on -K, which is SPSD).
+ *   b device [ne][N_phi]; it is projected onto the complement of the constant vector
+ *   (the kernel of K on a periodic or all-wall mesh) before the solve.
+ *   p device [ne][N_phi]; in: initial guess if params->warm_start, out: the solution with
+ *   int_Omega p dx = 0.
+ * Stopping rule: ||r_k||_2 <= rtol ||b||_2 on coefficient vectors; the true residual is
+ * recomputed at exit.  Blocks the calling thread until the solve ends (it synchronises
+ * `stream` every graph_block iterations to test convergence).  On SLD_E_NOCONV p holds
+ * the last iterate and the report is filled. */
+typedef struct {
+    double rtol;          /* relative residual tolerance, e.g. 1e-12 */
+    int32_t maxit;        /* iteration cap */
+    int32_t warm_start;   /* nonzero: p holds the initial guess */
+    int32_t graph_block;  /* iterations per convergence check (even, 2..4096) */
+    int32_t profile;      /* nonzero: time every CG kernel with HIP events on `stream` and
+                             report the averages (adds a small gap between launches) */
+} sld_cg_params;
+
+typedef struct {
+    int32_t iters;        /* CG iterations performed */
+    int32_t converged;    /* 1 if the recursive residual met rtol */
+    double rel_res;       /* recursive residual ||r_k|| / ||b|| */
+    double rel_res_true;  /* ||b - K p|| / ||b|| recomputed at exit */
+    double seconds;       /* wall time of the solve on the host */
+    double apply_us;      /* profile only: mean duration of the fused direction+apply kernel */
+    double update_us;     /* profile only: mean duration of the update kernel */
+    int32_t timed_iters;  /* profile only: iterations the means are taken over */
+    int32_t reserved;
+} sld_cg_report;
+
+sld_status sld_cg_solve(sld_disc disc, const double* b, double* p, const sld_cg_params* params,
+                        sld_cg_report* report, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLD_H */

@@ -189,3 +189,27 @@ def velocity_correction(disc: OracleDisc, v_star: np.ndarray, p_main: np.ndarray
                         coef: float) -> np.ndarray:
     """v = v* - coef * Mhat^{-1}(Q_l p_l + Q_r p_r), coef = a_ss dt (eq. nc.2 solved for v)."""
     return v_star - coef * gradient(disc, p_main)
+
+
+def schur_rows(disc: OracleDisc, p_main: np.ndarray, tri_ids) -> np.ndarray:
+    """(K p)_i for the triangles in tri_ids only, straight from eq. pressure_final:
+    sum over the triangle's interior edges of D_ij Mhat_j^{-1} (Q_lj p_l + Q_rj p_r).
+    Used to check large problems on a sample of rows without assembling K."""
+    m = disc.mesh
+    tri_ids = np.asarray(tri_ids, dtype=np.int64)
+    J = np.unique(m.tri_edges[tri_ids].ravel())
+    J = J[m.interior[J]]
+    Xl, Xr, blk = edge_solution_operators(disc, J)
+    g = np.einsum("ekmc,em->ekc", Xl, p_main[m.left[J]]) + \
+        np.einsum("ekmc,em->ekc", Xr, p_main[m.right[J]])  # [E, npsi, 2]
+    pos = {int(j): e for e, j in enumerate(J)}
+    out = np.zeros((tri_ids.size, disc.nphi))
+    for t, i in enumerate(tri_ids):
+        for alpha in range(3):
+            j = int(m.tri_edges[i, alpha])
+            if not m.interior[j]:
+                continue
+            e = pos[j]
+            Dm = blk["Dl"][e] if m.left[j] == i else blk["Dr"][e]
+            out[t] += np.einsum("kmc,mc->k", Dm, g[e])
+    return out

@@ -1,0 +1,598 @@
+// C ABI entry points: argument checking, host-side mesh setup (Section 2.1), reference
+// operators (Section 2.4), device buffers and the CG driver (Section 2.3).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "sld_internal.h"
+
+namespace {
+thread_local std::string g_err;
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+void dfree(T* p) {
+    if (p) (void)hipFree(p);
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+    return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (count ? count : 1));
+}
+
+void free_mesh(sld_mesh_s* m) {
+    if (!m) return;
+    dfree(m->geo);
+    dfree(m->nbr);
+    dfree(m->edges);
+    dfree(m->tedges);
+    delete m;
+}
+
+template <int P>
+size_t ops_size() { return sizeof(RefOps<P>); }
+
+int build_ops(int p, void** host, size_t* bytes) {
+    int rc = 0;
+    switch (p) {
+#define SLD_OPS_CASE(PP)                                          \
+    case PP: {                                                    \
+        RefOps<PP>* o = new (std::nothrow) RefOps<PP>();          \
+        if (!o) return -1;                                        \
+        rc = build_refops<PP>(o);                                 \
+        *host = o;                                                \
+        *bytes = sizeof(RefOps<PP>);                              \
+    } break;
+        SLD_OPS_CASE(1)
+        SLD_OPS_CASE(2)
+        SLD_OPS_CASE(3)
+        SLD_OPS_CASE(4)
+#undef SLD_OPS_CASE
+        default:
+            return -2;
+    }
+    return rc;
+}
+
+void free_ops_host(int p, void* h) {
+    switch (p) {
+        case 1: delete static_cast<RefOps<1>*>(h); break;
+        case 2: delete static_cast<RefOps<2>*>(h); break;
+        case 3: delete static_cast<RefOps<3>*>(h); break;
+        case 4: delete static_cast<RefOps<4>*>(h); break;
+        default: break;
+    }
+}
+
+const double* ops_w(const sld_disc_s* d) {
+    switch (d->p) {
+        case 1: return static_cast<const RefOps<1>*>(d->ops_host)->w;
+        case 2: return static_cast<const RefOps<2>*>(d->ops_host)->w;
+        case 3: return static_cast<const RefOps<3>*>(d->ops_host)->w;
+        case 4: return static_cast<const RefOps<4>*>(d->ops_host)->w;
+        default: return nullptr;
+    }
+}
+
+void free_disc(sld_disc_s* d) {
+    if (!d) return;
+    CgWork& w = d->cg;
+    dfree(w.x);
+    dfree(w.r);
+    dfree(w.d[0]);
+    dfree(w.d[1]);
+    dfree(w.q);
+    dfree(w.b);
+    dfree(w.partial);
+    dfree(w.scal);
+    dfree(w.counter);
+    if (w.host_scal) (void)hipHostFree(w.host_scal);
+    for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
+    dfree(d->ops_dev);
+    free_ops_host(d->p, d->ops_host);
+    delete d;
+}
+
+#define SLD_REQUIRE(cond, code, msg) \
+    do {                             \
+        if (!(cond)) {               \
+            sld_set_error(msg);      \
+            return code;             \
+        }                            \
+    } while (0)
+
+}  // namespace
+
+void sld_set_error(const std::string& msg) { g_err = msg; }
+
+extern "C" {
+
+const char* sld_last_error(void) { return g_err.c_str(); }
+
+int32_t sld_abi_version(void) { return 1; }
+
+sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int64_t ne,
+                           const double* period, int32_t device, sld_mesh* out) {
+    SLD_REQUIRE(out, SLD_E_INVALID, "sld_mesh_create: out is NULL");
+    *out = nullptr;
+    SLD_REQUIRE(xy && tri, SLD_E_INVALID, "sld_mesh_create: xy or tri is NULL");
+    SLD_REQUIRE(nv >= 3 && ne >= 1, SLD_E_INVALID, "sld_mesh_create: need nv >= 3 and ne >= 1");
+    SLD_REQUIRE(ne < (int64_t(1) << 28), SLD_E_BUDGET, "sld_mesh_create: ne must be < 2^28");
+    if (period) {
+        SLD_REQUIRE(std::isfinite(period[0]) && std::isfinite(period[1]) && period[0] > 0 &&
+                        period[1] > 0,
+                    SLD_E_INVALID, "sld_mesh_create: period must be positive and finite");
+    }
+    if (device != -1) {
+        int ndev = 0;
+        SLD_HIP_CHECK(hipGetDeviceCount(&ndev));
+        SLD_REQUIRE(device >= 0 && device < ndev, SLD_E_INVALID,
+                    "sld_mesh_create: bad device ordinal");
+    }
+
+    sld_mesh_s* m = new (std::nothrow) sld_mesh_s();
+    SLD_REQUIRE(m, SLD_E_NOMEM, "sld_mesh_create: host allocation failed");
+    m->device = device;
+    m->ne = ne;
+    m->nv = nv;
+    m->periodic = period != nullptr;
+    try {
+        m->P.resize(size_t(ne) * 6);
+        std::vector<double4> geo(ne);
+        double area = 0;
+        for (int64_t i = 0; i < ne; ++i) {
+            int32_t v[3] = {tri[3 * i], tri[3 * i + 1], tri[3 * i + 2]};
+            for (int k = 0; k < 3; ++k) {
+                if (v[k] < 0 || v[k] >= nv) {
+                    free_mesh(m);
+                    sld_set_error("sld_mesh_create: vertex id out of range in triangle " +
+                                  std::to_string(i));
+                    return SLD_E_MESH;
+                }
+            }
+            double x0 = xy[2 * v[0]], y0 = xy[2 * v[0] + 1];
+            double px[3], py[3];
+            for (int k = 0; k < 3; ++k) {
+                double x = xy[2 * v[k]], y = xy[2 * v[k] + 1];
+                if (period) {
+                    x -= period[0] * std::nearbyint((x - x0) / period[0]);
+                    y -= period[1] * std::nearbyint((y - y0) / period[1]);
+                }
+                px[k] = x;
+                py[k] = y;
+                m->P[6 * i + 2 * k] = x;
+                m->P[6 * i + 2 * k + 1] = y;
+            }
+            double e1x = px[1] - px[0], e1y = py[1] - py[0];
+            double e2x = px[2] - px[0], e2y = py[2] - py[0];
+            double det = e1x * e2y - e1y * e2x;
+            if (!(det > 0) || !std::isfinite(det)) {
+                free_mesh(m);
+                sld_set_error("sld_mesh_create: triangle " + std::to_string(i) +
+                              " has non-positive area (vertices must be counter-clockwise)");
+                return SLD_E_MESH;
+            }
+            area += 0.5 * det;
+            geo[i] = make_double4(e1x, e1y, e2x, e2y);
+        }
+        m->area_total = area;
+
+        // edges in order of first appearance
+        std::unordered_map<uint64_t, int32_t> edge_of;
+        edge_of.reserve(size_t(ne) * 2);
+        std::vector<int4> nbr(ne, make_int4(-1, -1, -1, 0));
+        std::vector<int4> tedges(ne, make_int4(0, 0, 0, 0));
+        m->tedge.assign(size_t(ne) * 3, -1);
+        for (int64_t i = 0; i < ne; ++i) {
+            for (int al = 0; al < 3; ++al) {
+                uint32_t va = (uint32_t)tri[3 * i + al], vb = (uint32_t)tri[3 * i + (al + 1) % 3];
+                if (va == vb) {
+                    free_mesh(m);
+                    sld_set_error("sld_mesh_create: degenerate edge in triangle " + std::to_string(i));
+                    return SLD_E_MESH;
+                }
+                uint64_t key = va < vb ? (uint64_t(va) << 32 | vb) : (uint64_t(vb) << 32 | va);
+                auto it = edge_of.find(key);
+                int32_t j;
+                if (it == edge_of.end()) {
+                    j = (int32_t)m->left.size();
+                    edge_of.emplace(key, j);
+                    m->left.push_back((int32_t)i);
+                    m->right.push_back(-1);
+                    m->alpha_l.push_back(al);
+                    m->alpha_r.push_back(-1);
+                } else {
+                    j = it->second;
+                    int32_t l = m->left[j], all = m->alpha_l[j];
+                    if (m->right[j] != -1) {
+                        free_mesh(m);
+                        sld_set_error("sld_mesh_create: non-manifold edge (more than two triangles)");
+                        return SLD_E_MESH;
+                    }
+                    if ((uint32_t)tri[3 * l + all] != vb || (uint32_t)tri[3 * l + (all + 1) % 3] != va) {
+                        free_mesh(m);
+                        sld_set_error("sld_mesh_create: inconsistent orientation across an edge");
+                        return SLD_E_MESH;
+                    }
+                    if (l == (int32_t)i) {
+                        free_mesh(m);
+                        sld_set_error("sld_mesh_create: an edge joins a triangle to itself");
+                        return SLD_E_MESH;
+                    }
+                    m->right[j] = (int32_t)i;
+                    m->alpha_r[j] = al;
+                }
+                m->tedge[3 * i + al] = j;
+            }
+        }
+        m->nd = (int64_t)m->left.size();
+        std::vector<int4> edges(m->nd);
+        m->shift.assign(size_t(m->nd) * 2, 0.0);
+        for (int64_t j = 0; j < m->nd; ++j) {
+            int32_t l = m->left[j], r = m->right[j], al = m->alpha_l[j], ar = m->alpha_r[j];
+            edges[j] = make_int4(l, r, al, ar);
+            int* nl = al == 0 ? &nbr[l].x : (al == 1 ? &nbr[l].y : &nbr[l].z);
+            int* tl = al == 0 ? &tedges[l].x : (al == 1 ? &tedges[l].y : &tedges[l].z);
+            *nl = pack_nbr(r, ar);
+            *tl = int(2 * j);
+            if (r >= 0) {
+                int* nr = ar == 0 ? &nbr[r].x : (ar == 1 ? &nbr[r].y : &nbr[r].z);
+                int* tr = ar == 0 ? &tedges[r].x : (ar == 1 ? &tedges[r].y : &tedges[r].z);
+                *nr = pack_nbr(l, al);
+                *tr = int(2 * j + 1);
+                // r's copy of B (its vertex ar) minus l's copy of B (l's vertex al+1)
+                for (int c = 0; c < 2; ++c) {
+                    double sB = m->P[6 * r + 2 * ar + c] - m->P[6 * l + 2 * ((al + 1) % 3) + c];
+                    double sA = m->P[6 * r + 2 * ((ar + 1) % 3) + c] - m->P[6 * l + 2 * al + c];
+                    double tol = 1e-9 * (1.0 + std::fabs(m->P[6 * l + 2 * al + c]));
+                    if (std::fabs(sA - sB) > tol || (!period && std::fabs(sA) > tol)) {
+                        free_mesh(m);
+                        sld_set_error("sld_mesh_create: neighbouring triangles disagree on an edge "
+                                      "(triangle larger than half a period?)");
+                        return SLD_E_MESH;
+                    }
+                    m->shift[2 * j + c] = sB;
+                }
+            }
+        }
+        if (device == -1) {
+            *out = m;  // host-only handle: tables and node queries, no device work
+            return SLD_OK;
+        }
+        DeviceGuard dg(device);
+        if (!dg.ok) {
+            free_mesh(m);
+            sld_set_error("sld_mesh_create: hipSetDevice failed");
+            return SLD_E_HIP;
+        }
+        hipError_t e = hipSuccess;
+        if (e == hipSuccess) e = dalloc(&m->geo, ne);
+        if (e == hipSuccess) e = dalloc(&m->nbr, ne);
+        if (e == hipSuccess) e = dalloc(&m->tedges, ne);
+        if (e == hipSuccess) e = dalloc(&m->edges, m->nd);
+        if (e == hipSuccess) e = hipMemcpy(m->geo, geo.data(), sizeof(double4) * ne, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->nbr, nbr.data(), sizeof(int4) * ne, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(m->tedges, tedges.data(), sizeof(int4) * ne, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(m->edges, edges.data(), sizeof(int4) * m->nd, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_mesh(m);
+            sld_set_error(std::string("sld_mesh_create: device setup failed: ") + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? SLD_E_NOMEM : SLD_E_HIP;
+        }
+    } catch (const std::bad_alloc&) {
+        free_mesh(m);
+        sld_set_error("sld_mesh_create: host allocation failed");
+        return SLD_E_NOMEM;
+    }
+    *out = m;
+    return SLD_OK;
+}
+
+sld_status sld_mesh_counts(sld_mesh m, int64_t* ne, int64_t* nd, int64_t* nv) {
+    SLD_REQUIRE(m, SLD_E_INVALID, "sld_mesh_counts: NULL mesh");
+    if (ne) *ne = m->ne;
+    if (nd) *nd = m->nd;
+    if (nv) *nv = m->nv;
+    return SLD_OK;
+}
+
+sld_status sld_mesh_edges(sld_mesh m, int32_t* left, int32_t* right, int32_t* alpha_left,
+                          int32_t* alpha_right) {
+    SLD_REQUIRE(m, SLD_E_INVALID, "sld_mesh_edges: NULL mesh");
+    const size_t n = size_t(m->nd) * sizeof(int32_t);
+    if (left) std::memcpy(left, m->left.data(), n);
+    if (right) std::memcpy(right, m->right.data(), n);
+    if (alpha_left) std::memcpy(alpha_left, m->alpha_l.data(), n);
+    if (alpha_right) std::memcpy(alpha_right, m->alpha_r.data(), n);
+    return SLD_OK;
+}
+
+void sld_mesh_destroy(sld_mesh m) {
+    if (!m) return;
+    if (m->device < 0) {
+        free_mesh(m);
+        return;
+    }
+    DeviceGuard dg(m->device);
+    free_mesh(m);
+}
+
+sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out) {
+    SLD_REQUIRE(out, SLD_E_INVALID, "sld_disc_create: out is NULL");
+    *out = nullptr;
+    SLD_REQUIRE(m, SLD_E_INVALID, "sld_disc_create: NULL mesh");
+    SLD_REQUIRE(p >= 1 && p <= 4, SLD_E_INVALID, "sld_disc_create: degree p must be in 1..4");
+    SLD_REQUIRE(flags == 0, SLD_E_INVALID, "sld_disc_create: flags must be 0");
+    sld_disc_s* d = new (std::nothrow) sld_disc_s();
+    SLD_REQUIRE(d, SLD_E_NOMEM, "sld_disc_create: host allocation failed");
+    d->mesh = m;
+    d->p = p;
+    d->nphi = (p + 1) * (p + 2) / 2;
+    d->npsi = (p + 1) * (p + 1);
+    int rc = build_ops(p, &d->ops_host, &d->ops_bytes);
+    if (rc != 0) {
+        free_disc(d);
+        sld_set_error("sld_disc_create: reference operator construction failed");
+        return rc == -1 ? SLD_E_NOMEM : SLD_E_INVALID;
+    }
+    if (m->device < 0) {
+        *out = d;  // host-only: reference operators and node queries only
+        return SLD_OK;
+    }
+    DeviceGuard dg(m->device);
+    const size_t nv = size_t(m->ne) * d->nphi;
+    const int nb = (int)((m->ne + 127) / 128);
+    CgWork& w = d->cg;
+    w.nblocks = nb;
+    hipError_t e = hipMalloc(&d->ops_dev, d->ops_bytes);
+    if (e == hipSuccess) e = hipMemcpy(d->ops_dev, d->ops_host, d->ops_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = dalloc(&w.x, nv);
+    if (e == hipSuccess) e = dalloc(&w.r, nv);
+    if (e == hipSuccess) e = dalloc(&w.d[0], nv);
+    if (e == hipSuccess) e = dalloc(&w.d[1], nv);
+    if (e == hipSuccess) e = dalloc(&w.q, nv);
+    if (e == hipSuccess) e = dalloc(&w.b, nv);
+    if (e == hipSuccess) e = dalloc(&w.partial, size_t(2) * nb);
+    if (e == hipSuccess) e = dalloc(&w.scal, CgScalars::NSCAL);
+    if (e == hipSuccess) e = dalloc(&w.counter, 4);
+    if (e == hipSuccess) e = hipMemset(w.counter, 0, 4 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(w.scal, 0, CgScalars::NSCAL * sizeof(double));
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), CgScalars::NSCAL * sizeof(double),
+                          hipHostMallocDefault);
+    if (e != hipSuccess) {
+        free_disc(d);
+        sld_set_error(std::string("sld_disc_create: device allocation failed: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SLD_E_NOMEM : SLD_E_HIP;
+    }
+    *out = d;
+    return SLD_OK;
+}
+
+sld_status sld_disc_info(sld_disc d, int32_t* p, int32_t* nphi, int32_t* npsi) {
+    SLD_REQUIRE(d, SLD_E_INVALID, "sld_disc_info: NULL disc");
+    if (p) *p = d->p;
+    if (nphi) *nphi = d->nphi;
+    if (npsi) *npsi = d->npsi;
+    return SLD_OK;
+}
+
+sld_status sld_main_nodes(sld_disc d, double* xy_out) {
+    SLD_REQUIRE(d && xy_out, SLD_E_INVALID, "sld_main_nodes: NULL argument");
+    const sld_mesh_s* m = d->mesh;
+    const int p = d->p;
+    for (int64_t i = 0; i < m->ne; ++i) {
+        const double* P = &m->P[6 * i];
+        int k = 0;
+        for (int b = 0; b <= p; ++b)
+            for (int a = 0; a <= p - b; ++a, ++k) {
+                double s = double(a) / p, t = double(b) / p;
+                for (int c = 0; c < 2; ++c)
+                    xy_out[(i * d->nphi + k) * 2 + c] =
+                        P[c] + s * (P[2 + c] - P[c]) + t * (P[4 + c] - P[c]);
+            }
+    }
+    return SLD_OK;
+}
+
+sld_status sld_dual_nodes(sld_disc d, double* xy_out) {
+    SLD_REQUIRE(d && xy_out, SLD_E_INVALID, "sld_dual_nodes: NULL argument");
+    const sld_mesh_s* m = d->mesh;
+    const int p = d->p;
+    for (int64_t j = 0; j < m->nd; ++j) {
+        const int l = m->left[j], r = m->right[j], al = m->alpha_l[j];
+        const double* Pl = &m->P[6 * l];
+        double A[2], B[2], bl[2], br[2];
+        for (int c = 0; c < 2; ++c) {
+            A[c] = Pl[2 * al + c];
+            B[c] = Pl[2 * ((al + 1) % 3) + c];
+            bl[c] = (Pl[c] + Pl[2 + c] + Pl[4 + c]) / 3.0;
+            br[c] = 0;
+            if (r >= 0) {
+                const double* Pr = &m->P[6 * r];
+                br[c] = (Pr[c] + Pr[2 + c] + Pr[4 + c]) / 3.0 - m->shift[2 * j + c];
+            }
+        }
+        for (int b = 0; b <= p; ++b)
+            for (int a = 0; a <= p; ++a) {
+                const int k = b * (p + 1) + a;
+                const double s = double(a) / p, t = double(b) / p;
+                for (int c = 0; c < 2; ++c) {
+                    double v;
+                    if (a + b <= p) v = bl[c] + s * (A[c] - bl[c]) + t * (B[c] - bl[c]);
+                    else if (r >= 0) v = br[c] + (1 - t) * (A[c] - br[c]) + (1 - s) * (B[c] - br[c]);
+                    else v = NAN;
+                    xy_out[(j * d->npsi + k) * 2 + c] = v;
+                }
+            }
+    }
+    return SLD_OK;
+}
+
+sld_status sld_main_weights(sld_disc d, double* w_out) {
+    SLD_REQUIRE(d && w_out, SLD_E_INVALID, "sld_main_weights: NULL argument");
+    const sld_mesh_s* m = d->mesh;
+    const double* w = ops_w(d);
+    for (int64_t i = 0; i < m->ne; ++i) {
+        const double* P = &m->P[6 * i];
+        const double A = (P[2] - P[0]) * (P[5] - P[1]) - (P[3] - P[1]) * (P[4] - P[0]);
+        for (int k = 0; k < d->nphi; ++k) w_out[i * d->nphi + k] = A * w[k];
+    }
+    return SLD_OK;
+}
+
+void sld_disc_destroy(sld_disc d) {
+    if (!d) return;
+    if (d->mesh->device < 0) {
+        free_disc(d);
+        return;
+    }
+    DeviceGuard dg(d->mesh->device);
+    free_disc(d);
+}
+
+#define SLD_REQUIRE_DEVICE(d, fn) \
+    SLD_REQUIRE((d)->mesh->device >= 0, SLD_E_INVALID, fn ": handle was created host-only (device -1)")
+
+sld_status sld_schur_apply(sld_disc d, const double* p, double* Kp, void* stream) {
+    SLD_REQUIRE(d && p && Kp, SLD_E_INVALID, "sld_schur_apply: NULL argument");
+    SLD_REQUIRE(p != Kp, SLD_E_INVALID, "sld_schur_apply: p and Kp must not alias");
+    SLD_REQUIRE_DEVICE(d, "sld_schur_apply");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_schur_apply(d, p, Kp, 1.0, (hipStream_t)stream));
+    return SLD_OK;
+}
+
+sld_status sld_gradient(sld_disc d, const double* p, double* g, void* stream) {
+    SLD_REQUIRE(d && p && g, SLD_E_INVALID, "sld_gradient: NULL argument");
+    SLD_REQUIRE_DEVICE(d, "sld_gradient");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_gradient(d, p, nullptr, 1.0, g, (hipStream_t)stream));
+    return SLD_OK;
+}
+
+sld_status sld_divergence(sld_disc d, const double* v, double* out, void* stream) {
+    SLD_REQUIRE(d && v && out, SLD_E_INVALID, "sld_divergence: NULL argument");
+    SLD_REQUIRE_DEVICE(d, "sld_divergence");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_divergence(d, v, 1.0, out, (hipStream_t)stream));
+    return SLD_OK;
+}
+
+sld_status sld_pressure_rhs(sld_disc d, const double* v_star, double scale, double* b, void* stream) {
+    SLD_REQUIRE(d && v_star && b, SLD_E_INVALID, "sld_pressure_rhs: NULL argument");
+    SLD_REQUIRE(std::isfinite(scale), SLD_E_INVALID, "sld_pressure_rhs: scale must be finite");
+    SLD_REQUIRE_DEVICE(d, "sld_pressure_rhs");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_divergence(d, v_star, scale, b, (hipStream_t)stream));
+    return SLD_OK;
+}
+
+sld_status sld_velocity_correct(sld_disc d, const double* v_star, const double* p, double coef,
+                                double* v, void* stream) {
+    SLD_REQUIRE(d && v_star && p && v, SLD_E_INVALID, "sld_velocity_correct: NULL argument");
+    SLD_REQUIRE(std::isfinite(coef), SLD_E_INVALID, "sld_velocity_correct: coef must be finite");
+    SLD_REQUIRE_DEVICE(d, "sld_velocity_correct");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_gradient(d, p, v_star, -coef, v, (hipStream_t)stream));
+    return SLD_OK;
+}
+
+sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_params* prm,
+                        sld_cg_report* rep, void* stream) {
+    SLD_REQUIRE(d && b && p && prm, SLD_E_INVALID, "sld_cg_solve: NULL argument");
+    SLD_REQUIRE(prm->rtol > 0 && std::isfinite(prm->rtol), SLD_E_INVALID,
+                "sld_cg_solve: rtol must be positive");
+    SLD_REQUIRE(prm->maxit >= 1, SLD_E_INVALID, "sld_cg_solve: maxit must be >= 1");
+    SLD_REQUIRE(prm->graph_block >= 2 && prm->graph_block % 2 == 0 && prm->graph_block <= 4096,
+                SLD_E_INVALID, "sld_cg_solve: graph_block must be even and in [2, 4096]");
+    SLD_REQUIRE_DEVICE(d, "sld_cg_solve");
+    DeviceGuard dg(d->mesh->device);
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    CgWork& w = d->cg;
+    SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, s));
+    typedef CgScalars S;
+    const bool prof = prm->profile != 0;
+    const int gb = prm->graph_block;
+    if (prof && (int)w.events.size() < 2 * gb + 1) {
+        for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
+        w.events.assign(2 * gb + 1, nullptr);
+        for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
+    }
+    int iters = 0, done = 0, timed = 0;
+    double t_apply = 0, t_update = 0;
+    while (true) {
+        if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[0], s));
+        for (int k = 0; k < gb; ++k) {
+            SLD_HIP_CHECK(launch_cg_apply_only(d, k & 1, s));
+            if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[2 * k + 1], s));
+            SLD_HIP_CHECK(launch_cg_update_only(d, k & 1, s));
+            if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[2 * k + 2], s));
+        }
+        SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
+                                     hipMemcpyDeviceToHost, s));
+        SLD_HIP_CHECK(hipStreamSynchronize(s));
+        const int before = iters;
+        iters = (int)w.host_scal[S::ITER];
+        done = (int)w.host_scal[S::DONE];
+        if (prof) {
+            const int nk = iters - before;  // iterations that did work in this block
+            for (int k = 0; k < nk && k < gb; ++k) {
+                float a = 0, u = 0;
+                SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[2 * k], w.events[2 * k + 1]));
+                SLD_HIP_CHECK(hipEventElapsedTime(&u, w.events[2 * k + 1], w.events[2 * k + 2]));
+                t_apply += a;
+                t_update += u;
+                ++timed;
+            }
+        }
+        if (done) break;
+    }
+    const double rr = w.host_scal[S::RR], bb = w.host_scal[S::BB];
+    SLD_HIP_CHECK(launch_cg_finish(d, p, s));
+    SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    SLD_HIP_CHECK(hipStreamSynchronize(s));
+    const double rt = w.host_scal[S::FLAG];
+    if (rep) {
+        rep->iters = iters;
+        rep->converged = done == 1;
+        rep->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        rep->rel_res_true = bb > 0 ? std::sqrt(rt / bb) : 0.0;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        rep->apply_us = timed ? 1e3 * t_apply / timed : 0.0;
+        rep->update_us = timed ? 1e3 * t_update / timed : 0.0;
+        rep->timed_iters = timed;
+        rep->reserved = 0;
+    }
+    if (done == 3) {
+        sld_set_error("sld_cg_solve: breakdown (d.Ad <= 0 or non-finite)");
+        return SLD_E_BREAKDOWN;
+    }
+    if (done == 2) {
+        sld_set_error("sld_cg_solve: maxit reached before rtol");
+        return SLD_E_NOCONV;
+    }
+    return SLD_OK;
+}
+
+}  // extern "C"

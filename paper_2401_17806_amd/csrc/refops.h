@@ -1,0 +1,50 @@
+// Reference operators of degree P on the reference triangle (Section 2.4), in the
+// triangle-centred form the kernels use.  Filled on the host in float64 by exact Gauss
+// quadrature (refops.cpp), copied once to the device.
+//
+// Notation (reference triangle T_ref with vertices v0=(0,0), v1=(1,0), v2=(0,1), centroid c):
+//   local edge alpha runs v_alpha -> v_{alpha+1}; its p+1 Lagrange nodes are numbered
+//   m = 0..p from v_alpha.  The sub-triangle T^alpha = (c, v_alpha, v_{alpha+1}) is the image
+//   of a triangle's half of the dual cell of edge alpha; its local coordinates zeta put
+//   (0,0) at c, (1,0) at v_alpha, (0,1) at v_{alpha+1}, and its Lagrange nodes (a,b) use the
+//   main numbering.  Nodes with a+b = p ("H", on the edge) are numbered by m = b; the others
+//   are the interior set "I".
+#pragma once
+
+template <int P>
+struct RefOps {
+    static constexpr int NPHI = (P + 1) * (P + 2) / 2;
+    static constexpr int NE = P + 1;          // nodes on one edge
+    static constexpr int NI = NPHI - NE;      // sub-triangle nodes off the edge
+    // int_{T_ref} d_d phi_k d_e phi_l: [0] = (xi,xi), [1] = (xi,eta)+(eta,xi), [2] = (eta,eta)
+    double S[3][NPHI][NPHI];
+    // the same integrals restricted to sub-triangle T^alpha (wall edges)
+    double Sh[3][3][NPHI][NPHI];
+    // E[alpha][d][m][l] = d_d phi_l at edge node m of edge alpha
+    double E[3][2][NE][NPHI];
+    // Pt[alpha][d][k][m] = int_{T^alpha} d_d phi_k chi_m, chi_m = sub-triangle polynomial equal
+    // to 1 at edge node m, 0 at the other edge nodes and -Z[:,m] at the interior nodes
+    double Pt[3][2][NPHI][NE];
+    // Hn[alpha][d][n][l] = d_d phi_l at sub-triangle node n (main numbering in zeta) of T^alpha
+    double Hn[3][2][NPHI][NPHI];
+    // W[alpha][d][k][n] = int_{T^alpha} d_d phi_k phi_n(zeta)  (phi_n: sub-triangle Lagrange basis)
+    double W[3][2][NPHI][NPHI];
+    // Z = M_II^{-1} M_IH (sub-triangle mass matrix blocks), I in main order, H by m
+    double Z[NI > 0 ? NI : 1][NE];
+    // C = S0^{-1} M1, S0 = M_HH - M_HI Z (interface Schur complement), M1 = 1D edge mass
+    double C[NE][NE];
+    double M1[NE][NE];
+    // int_{T_ref} phi_k
+    double w[NPHI];
+};
+
+// Fill ops for degree P (1..4).  Returns 0 on success.
+template <int P>
+int build_refops(RefOps<P>* ops);
+
+// Main node index of lattice node (a, b), b outer / a inner.
+constexpr int main_idx(int P, int a, int b) { return b * (P + 1) - (b * (b - 1)) / 2 + a; }
+// Main index of node m (0..P) on local edge alpha, counted from v_alpha.
+constexpr int edge_node(int P, int alpha, int m) {
+    return alpha == 0 ? main_idx(P, m, 0) : (alpha == 1 ? main_idx(P, P - m, m) : main_idx(P, 0, P - m));
+}

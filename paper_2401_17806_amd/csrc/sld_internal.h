@@ -1,0 +1,88 @@
+// Internal state of the library: mesh and discretisation handles, error helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sld.h"
+#include "refops.h"
+
+// Thread-local error message (sld_last_error).
+void sld_set_error(const std::string& msg);
+
+#define SLD_HIP_CHECK(expr)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            sld_set_error(std::string(#expr) + ": " + hipGetErrorString(e_));            \
+            return SLD_E_HIP;                                                            \
+        }                                                                                \
+    } while (0)
+
+// Neighbour entry packing: (triangle << 2) | local edge in that triangle; -1 = wall.
+inline int32_t pack_nbr(int32_t tri, int32_t alpha) { return tri < 0 ? -1 : (tri << 2) | alpha; }
+
+struct sld_mesh_s {
+    int device = 0;
+    int64_t ne = 0, nd = 0, nv = 0;
+    bool periodic = false;
+    // host copies
+    std::vector<double> P;         // [ne][3][2] unwrapped vertex coordinates
+    std::vector<int32_t> left, right, alpha_l, alpha_r;  // [nd]
+    std::vector<int32_t> tedge;    // [ne][3] edge id of local edge alpha
+    std::vector<double> shift;     // [nd][2] r's frame minus l's frame
+    // device
+    double4* geo = nullptr;        // [ne] (e1x, e1y, e2x, e2y): e1 = P1-P0, e2 = P2-P0
+    int4* nbr = nullptr;           // [ne] packed neighbour across local edges 0,1,2; w unused
+    int4* edges = nullptr;         // [nd] (l, r, alpha_l, alpha_r)
+    int4* tedges = nullptr;        // [ne] (2*j + beta) per local edge; beta = 1 if i = r(j)
+    double area_total = 0;         // |Omega|
+};
+
+// Workspace of the CG solver (allocated with the disc).
+struct CgWork {
+    double* x = nullptr;
+    double* r = nullptr;
+    double* d[2] = {nullptr, nullptr};
+    double* q = nullptr;
+    double* b = nullptr;           // projected right-hand side
+    double* partial = nullptr;     // per-block partial sums
+    double* scal = nullptr;        // device scalars (see cg kernels)
+    unsigned* counter = nullptr;   // last-block counters
+    double* host_scal = nullptr;   // pinned mirror of scal
+    int nblocks = 0;
+    std::vector<hipEvent_t> events;  // profiling events (created on first profiled solve)
+};
+
+struct sld_disc_s {
+    sld_mesh mesh = nullptr;
+    int p = 0, nphi = 0, npsi = 0;
+    void* ops_dev = nullptr;       // RefOps<p> on the device
+    void* ops_host = nullptr;      // RefOps<p> on the host
+    size_t ops_bytes = 0;
+    CgWork cg;
+};
+
+// Kernel launchers (kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_schur_apply(const sld_disc_s* d, const double* p, double* out, double scale,
+                              hipStream_t s);
+hipError_t launch_gradient(const sld_disc_s* d, const double* p, const double* vstar, double coef,
+                           double* out, hipStream_t s);
+hipError_t launch_divergence(const sld_disc_s* d, const double* v, double scale, double* out,
+                             hipStream_t s);
+
+// CG building blocks (kernels.hip)
+struct CgScalars {
+    // layout of CgWork::scal (doubles): see kernels.hip
+    enum { RR = 0, BB = 1, ALPHA = 2, BETA = 3, DQ = 4, TOL2 = 5, ITER = 6, DONE = 7,
+           MAXIT = 8, FLAG = 9, MEAN = 10, NSCAL = 16 };
+};
+hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
+                           double rtol, int maxit, hipStream_t s);
+hipError_t launch_cg_iteration(const sld_disc_s* d, int parity, hipStream_t s);
+hipError_t launch_cg_apply_only(const sld_disc_s* d, int parity, hipStream_t s);
+hipError_t launch_cg_update_only(const sld_disc_s* d, int parity, hipStream_t s);
+hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s);

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of libsld.so (the C ABI declared in include/sld.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are torch tensors (float64, contiguous, on the
+handle's device); the current torch stream of that device is passed as the
+HIP stream.  Shapes, dtypes and devices are checked here, on the host,
+before any launch.  There is no fallback: if the library is missing the
+import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsld.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2401_17806_amd.build` "
+        "(hipcc, gfx950); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+_c_ip = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+
+
+class sld_cg_params(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("maxit", _i32), ("warm_start", _i32),
+                ("graph_block", _i32), ("profile", _i32)]
+
+
+class sld_cg_report(ctypes.Structure):
+    _fields_ = [("iters", _i32), ("converged", _i32), ("rel_res", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("apply_us", ctypes.c_double), ("update_us", ctypes.c_double),
+                ("timed_iters", _i32), ("reserved", _i32)]
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_lib.sld_last_error.restype = ctypes.c_char_p
+_lib.sld_last_error.argtypes = []
+_sig("sld_abi_version", [], _i32)
+_sig("sld_mesh_create", [_c_dp, _i64, _c_ip, _i64, _c_dp, _i32, ctypes.POINTER(_vp)])
+_sig("sld_mesh_counts", [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)])
+_sig("sld_mesh_edges", [_vp, _c_ip, _c_ip, _c_ip, _c_ip])
+_sig("sld_mesh_destroy", [_vp], None)
+_sig("sld_disc_create", [_vp, _i32, ctypes.c_uint32, ctypes.POINTER(_vp)])
+_sig("sld_disc_info", [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)])
+_sig("sld_main_nodes", [_vp, _c_dp])
+_sig("sld_dual_nodes", [_vp, _c_dp])
+_sig("sld_main_weights", [_vp, _c_dp])
+_sig("sld_disc_destroy", [_vp], None)
+_sig("sld_schur_apply", [_vp, _vp, _vp, _vp])
+_sig("sld_gradient", [_vp, _vp, _vp, _vp])
+_sig("sld_divergence", [_vp, _vp, _vp, _vp])
+_sig("sld_pressure_rhs", [_vp, _vp, ctypes.c_double, _vp, _vp])
+_sig("sld_velocity_correct", [_vp, _vp, _vp, ctypes.c_double, _vp, _vp])
+_sig("sld_cg_solve", [_vp, _vp, _vp, ctypes.POINTER(sld_cg_params),
+                      ctypes.POINTER(sld_cg_report), _vp])
+
+EXPORTED = [
+    "sld_last_error", "sld_abi_version", "sld_mesh_create", "sld_mesh_counts", "sld_mesh_edges",
+    "sld_mesh_destroy", "sld_disc_create", "sld_disc_info", "sld_main_nodes", "sld_dual_nodes",
+    "sld_main_weights", "sld_disc_destroy", "sld_schur_apply", "sld_gradient", "sld_divergence",
+    "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve",
+]
+
+STATUS = {0: "SLD_OK", 1: "SLD_E_INVALID", 2: "SLD_E_MESH", 3: "SLD_E_NOMEM", 4: "SLD_E_HIP",
+          5: "SLD_E_NOCONV", 6: "SLD_E_BREAKDOWN", 7: "SLD_E_BUDGET"}
+
+
+class SldError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status):
+    if status != 0:
+        raise SldError(status, _lib.sld_last_error().decode(errors="replace"))
+
+
+def sld_last_error() -> str:
+    return _lib.sld_last_error().decode(errors="replace")
+
+
+def sld_abi_version() -> int:
+    return int(_lib.sld_abi_version())
+
+
+def _host_f64(a, shape_tail=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_c_dp)
+
+
+# ---------------------------------------------------------------- raw C-named wrappers
+def sld_mesh_create(xy, tri, period=None, device: int = 0):
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float64))
+    tri = np.ascontiguousarray(np.asarray(tri, dtype=np.int32))
+    if xy.ndim != 2 or xy.shape[1] != 2 or tri.ndim != 2 or tri.shape[1] != 3:
+        raise ValueError("xy must be [nv, 2] and tri [ne, 3]")
+    per = None if period is None else np.ascontiguousarray(np.asarray(period, dtype=np.float64))
+    if per is not None and per.shape != (2,):
+        raise ValueError("period must have shape (2,)")
+    h = _vp()
+    _check(_lib.sld_mesh_create(_dptr(xy), xy.shape[0], tri.ctypes.data_as(_c_ip), tri.shape[0],
+                                None if per is None else _dptr(per), int(device), ctypes.byref(h)))
+    return h
+
+
+def sld_mesh_counts(h):
+    ne, nd, nv = _i64(), _i64(), _i64()
+    _check(_lib.sld_mesh_counts(h, ctypes.byref(ne), ctypes.byref(nd), ctypes.byref(nv)))
+    return ne.value, nd.value, nv.value
+
+
+def sld_mesh_edges(h):
+    _, nd, _ = sld_mesh_counts(h)
+    arrs = [np.empty(nd, dtype=np.int32) for _ in range(4)]
+    _check(_lib.sld_mesh_edges(h, *[a.ctypes.data_as(_c_ip) for a in arrs]))
+    return tuple(arrs)
+
+
+def sld_mesh_destroy(h):
+    _lib.sld_mesh_destroy(h)
+
+
+def sld_disc_create(mesh_h, p: int):
+    h = _vp()
+    _check(_lib.sld_disc_create(mesh_h, int(p), 0, ctypes.byref(h)))
+    return h
+
+
+def sld_disc_info(h):
+    p, nphi, npsi = _i32(), _i32(), _i32()
+    _check(_lib.sld_disc_info(h, ctypes.byref(p), ctypes.byref(nphi), ctypes.byref(npsi)))
+    return p.value, nphi.value, npsi.value
+
+
+def sld_disc_destroy(h):
+    _lib.sld_disc_destroy(h)
+
+
+class Mesh:
+    """Owner of an sld_mesh handle."""
+
+    def __init__(self, xy, tri, period=None, device: int = 0):
+        self.device = int(device)
+        self.handle = sld_mesh_create(xy, tri, period, device)
+        self.ne, self.nd, self.nv = sld_mesh_counts(self.handle)
+
+    def edges(self):
+        return sld_mesh_edges(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            sld_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Disc:
+    """Owner of an sld_disc handle; operator entry points take torch device tensors."""
+
+    def __init__(self, mesh: Mesh, p: int):
+        self.mesh = mesh
+        self.handle = sld_disc_create(mesh.handle, p)
+        self.p, self.nphi, self.npsi = sld_disc_info(self.handle)
+        self.main_shape = (mesh.ne, self.nphi)
+        self.dual_shape = (mesh.nd, 2, self.npsi)
+
+    # -------------------------------------------------------- host queries
+    def main_nodes(self):
+        out = np.empty((self.mesh.ne, self.nphi, 2))
+        _check(_lib.sld_main_nodes(self.handle, _dptr(out)))
+        return out
+
+    def dual_nodes(self):
+        out = np.empty((self.mesh.nd, self.npsi, 2))
+        _check(_lib.sld_dual_nodes(self.handle, _dptr(out)))
+        return out
+
+    def main_weights(self):
+        out = np.empty((self.mesh.ne, self.nphi))
+        _check(_lib.sld_main_weights(self.handle, _dptr(out)))
+        return out
+
+    # -------------------------------------------------------- device helpers
+    def _dev(self, t, shape, name):
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != torch.float64 or not t.is_cuda or t.device.index != self.mesh.device:
+            raise ValueError(f"{name} must be float64 on cuda:{self.mesh.device}")
+        if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}, got {tuple(t.shape)}")
+        return _vp(t.data_ptr())
+
+    def _stream(self, stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.mesh.device)
+        return _vp(s.cuda_stream)
+
+    def _new(self, shape):
+        import torch
+        return torch.empty(shape, dtype=torch.float64, device=f"cuda:{self.mesh.device}")
+
+    # -------------------------------------------------------- operators
+    def sld_schur_apply(self, p, out=None, stream=None):
+        out = self._new(self.main_shape) if out is None else out
+        _check(_lib.sld_schur_apply(self.handle, self._dev(p, self.main_shape, "p"),
+                                    self._dev(out, self.main_shape, "Kp"), self._stream(stream)))
+        return out
+
+    def sld_gradient(self, p, out=None, stream=None):
+        out = self._new(self.dual_shape) if out is None else out
+        _check(_lib.sld_gradient(self.handle, self._dev(p, self.main_shape, "p"),
+                                 self._dev(out, self.dual_shape, "g"), self._stream(stream)))
+        return out
+
+    def sld_divergence(self, v, out=None, stream=None):
+        out = self._new(self.main_shape) if out is None else out
+        _check(_lib.sld_divergence(self.handle, self._dev(v, self.dual_shape, "v"),
+                                   self._dev(out, self.main_shape, "out"), self._stream(stream)))
+        return out
+
+    def sld_pressure_rhs(self, v_star, scale, out=None, stream=None):
+        out = self._new(self.main_shape) if out is None else out
+        _check(_lib.sld_pressure_rhs(self.handle, self._dev(v_star, self.dual_shape, "v_star"),
+                                     float(scale), self._dev(out, self.main_shape, "b"),
+                                     self._stream(stream)))
+        return out
+
+    def sld_velocity_correct(self, v_star, p, coef, out=None, stream=None):
+        out = self._new(self.dual_shape) if out is None else out
+        _check(_lib.sld_velocity_correct(self.handle, self._dev(v_star, self.dual_shape, "v_star"),
+                                         self._dev(p, self.main_shape, "p"), float(coef),
+                                         self._dev(out, self.dual_shape, "v"), self._stream(stream)))
+        return out
+
+    def sld_cg_solve(self, b, p=None, rtol=1e-12, maxit=100000, warm_start=False,
+                     graph_block=32, profile=False, stream=None):
+        p = self._new(self.main_shape) if p is None else p
+        prm = sld_cg_params(float(rtol), int(maxit), int(bool(warm_start)), int(graph_block),
+                            int(bool(profile)))
+        rep = sld_cg_report()
+        st = _lib.sld_cg_solve(self.handle, self._dev(b, self.main_shape, "b"),
+                               self._dev(p, self.main_shape, "p"), ctypes.byref(prm),
+                               ctypes.byref(rep), self._stream(stream))
+        report = {"iters": rep.iters, "converged": bool(rep.converged), "rel_res": rep.rel_res,
+                  "rel_res_true": rep.rel_res_true, "seconds": rep.seconds,
+                  "apply_us": rep.apply_us, "update_us": rep.update_us,
+                  "timed_iters": rep.timed_iters, "status": STATUS.get(st, st)}
+        if st not in (0, 5):
+            _check(st)
+        return p, report
+
+    def close(self):
+        if getattr(self, "handle", None):
+            sld_disc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,84 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and its
+host-side mesh setup (edge table, node positions, gauge weights) matches the oracle.
+No device computation is run here (handles are created host-only, device = -1)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.mesh import OracleMesh
+from oracle.operators import OracleDisc
+from paper_2401_17806_amd.inputs import lattice_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "sld.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sld_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2401_17806_amd import sld
+    lib = ctypes.CDLL(sld.LIB_PATH)
+    names = _declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(sld.EXPORTED) == set(names)
+    assert sld.sld_abi_version() == 1
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_edge_table_matches_oracle(periodic):
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(6, seed=5, periodic=periodic)
+    m = sld.Mesh(xy, tri, per, device=-1)
+    om = OracleMesh(xy, tri, per)
+    l, r, al, ar = m.edges()
+    assert (m.ne, m.nd, m.nv) == (om.ne, om.nd, om.nv)
+    assert (l == om.left).all() and (r == om.right).all()
+    assert (al == om.alpha_l).all() and (ar == om.alpha_r).all()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_nodes_and_weights_match_oracle(p):
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(5, seed=7)
+    m = sld.Mesh(xy, tri, per, device=-1)
+    d = sld.Disc(m, p)
+    od = OracleDisc(OracleMesh(xy, tri, per), p)
+    assert np.abs(d.main_nodes() - od.main_node_xy()).max() < 1e-14
+    assert np.abs(d.dual_nodes() - od.dual_node_xy()).max() < 1e-14
+    assert np.abs(d.main_weights() - od.main_weights()).max() < 1e-14
+
+
+def test_mesh_validation_errors():
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(4, seed=1)
+    bad = tri.copy()
+    bad[3] = bad[3][::-1]
+    with pytest.raises(sld.SldError) as e:
+        sld.Mesh(xy, bad, per, device=-1)
+    assert e.value.status == 2
+    bad = tri.copy()
+    bad[0, 0] = 10_000
+    with pytest.raises(sld.SldError):
+        sld.Mesh(xy, bad, per, device=-1)
+    m = sld.Mesh(xy, tri, per, device=-1)
+    for p in (0, 5):
+        with pytest.raises(sld.SldError) as e:
+            sld.Disc(m, p)
+        assert e.value.status == 1
+
+
+def test_host_only_handle_refuses_device_work():
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(4, seed=1)
+    m = sld.Mesh(xy, tri, per, device=-1)
+    d = sld.Disc(m, 2)
+    st = sld._lib.sld_schur_apply(d.handle, ctypes.c_void_p(8), ctypes.c_void_p(16), None)
+    assert st == 1 and "host-only" in sld.sld_last_error()
