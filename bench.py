@@ -36,15 +36,21 @@ FP64_PEAK_TFLOPS = 78.6
 A_SS = 0.43586652150845967
 
 
-def apply_bytes_per_tri(nphi: int) -> int:
-    # fused direction + apply kernel: read r, d_old; write d_new, q (8 B each per DOF);
-    # geometry 32 B (two edge vectors) + neighbour table 16 B
-    return 4 * 8 * nphi + 48
+def step_bytes_per_tri(nphi: int) -> int:
+    # one CG iteration kernel (k_cg_step): read x, r, q, d and write x, r, q, d (8 B per DOF
+    # each) plus the geometry (two edge vectors, 32 B) and the neighbour table (16 B)
+    return 8 * 8 * nphi + 48
 
 
-def iteration_bytes_per_tri(nphi: int) -> int:
-    # apply kernel above + update kernel (read x, d, r, q; write x, r)
-    return apply_bytes_per_tri(nphi) + 6 * 8 * nphi
+def step_flops_per_tri(p: int) -> int:
+    # FP64 flops of one iteration per triangle (FMA = 2), counted from the operator form:
+    # volume 3 N^2, per edge: edge-node gradients of both sides 4 (p+1) N, jump 2 (p+1)^2,
+    # line 2 (p+1)^2... plus the vector updates; see the design notes for the derivation
+    n = (p + 1) * (p + 2) // 2
+    ne = p + 1
+    per_edge = 4 * ne * n + 2 * ne * ne + 2 * n * ne + 16 * ne
+    fma = 3 * n * n + 3 * per_edge + 8 * n + 4 * 2 * n
+    return 2 * fma
 
 
 def cpu_baseline(wl, xy, tri, per, b_host, iters=200):
@@ -79,7 +85,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--rtol", type=float, default=1e-12)
-    ap.add_argument("--graph-block", type=int, default=32)
+    ap.add_argument("--graph-block", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -133,16 +139,15 @@ def main():
     divfree = float(torch.linalg.norm(div) / torch.linalg.norm(div0))
 
     timed = sum(r["timed_iters"] for r in reps)
-    apply_us = sum(r["apply_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
-    update_us = sum(r["update_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
-    abytes = apply_bytes_per_tri(nphi) * ne
-    achieved = abytes / (apply_us * 1e-6) / 1e9
+    step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
+    sbytes = step_bytes_per_tri(nphi) * ne
+    achieved = sbytes / (step_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_cg_apply (direction + Schur apply + d.q)",
-                "kernel_us": apply_us, "bytes_per_launch": abytes,
-                "update_kernel_us": update_us,
-                "iteration_GBs": iteration_bytes_per_tri(nphi) * ne / ((apply_us + update_us) * 1e-6) / 1e9}
+                "kernel": f"k_cg_step<{p}> (one fused CG iteration)",
+                "kernel_us": step_us, "bytes_per_launch": sbytes,
+                "fp64_tflops": step_flops_per_tri(p) * ne / (step_us * 1e-6) / 1e12,
+                "fp64_peak_tflops": FP64_PEAK_TFLOPS}
 
     out = {
         "metric": "Schur-CG DOF-updates/s at 1e-9 rel. error vs FP64 oracle; p50/p99 solve latency",

@@ -130,16 +130,20 @@ sld_status sld_velocity_correct(sld_disc disc, const double* v_star, const doubl
  *   p device [ne][N_phi]; in: initial guess if params->warm_start, out: the solution with
  *   int_Omega p dx = 0.
  * Stopping rule: ||r_k||_2 <= rtol ||b||_2 on coefficient vectors; the true residual is
- * recomputed at exit.  Blocks the calling thread until the solve ends (it synchronises
- * `stream` every graph_block iterations to test convergence).  On SLD_E_NOCONV p holds
+ * recomputed at exit.  Iterations run as a captured HIP graph of graph_block iterations
+ * (scalars stay on the device); the calling thread blocks until the solve ends and
+ * synchronises `stream` once per graph to test convergence.  Results are deterministic
+ * (fixed-order reductions, no atomics).  On SLD_E_NOCONV p holds
  * the last iterate and the report is filled. */
 typedef struct {
     double rtol;          /* relative residual tolerance, e.g. 1e-12 */
     int32_t maxit;        /* iteration cap */
     int32_t warm_start;   /* nonzero: p holds the initial guess */
     int32_t graph_block;  /* iterations per convergence check (even, 2..4096) */
-    int32_t profile;      /* nonzero: time every CG kernel with HIP events on `stream` and
-                             report the averages (adds a small gap between launches) */
+    int32_t profile;      /* nonzero: launch the iterations one by one (no graph) with a HIP
+                             event after each on `stream`; the report gives the mean time
+                             between consecutive iteration kernels */
+    int32_t reserved;     /* pass 0 */
 } sld_cg_params;
 
 typedef struct {
@@ -148,9 +152,8 @@ typedef struct {
     double rel_res;       /* recursive residual ||r_k|| / ||b|| */
     double rel_res_true;  /* ||b - K p|| / ||b|| recomputed at exit */
     double seconds;       /* wall time of the solve on the host */
-    double apply_us;      /* profile only: mean duration of the fused direction+apply kernel */
-    double update_us;     /* profile only: mean duration of the update kernel */
-    int32_t timed_iters;  /* profile only: iterations the means are taken over */
+    double step_us;       /* profile only: mean duration of one CG iteration kernel */
+    int32_t timed_iters;  /* profile only: iterations the mean is taken over */
     int32_t reserved;
 } sld_cg_report;
 

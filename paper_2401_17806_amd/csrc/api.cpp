@@ -1,5 +1,6 @@
 // C ABI entry points: argument checking, host-side mesh setup (Section 2.1), reference
 // operators (Section 2.4), device buffers and the CG driver (Section 2.3).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -94,14 +95,17 @@ void free_disc(sld_disc_s* d) {
     if (!d) return;
     CgWork& w = d->cg;
     dfree(w.x);
-    dfree(w.r);
-    dfree(w.d[0]);
-    dfree(w.d[1]);
-    dfree(w.q);
+    for (int k = 0; k < 2; ++k) {
+        dfree(w.r[k]);
+        dfree(w.q[k]);
+        dfree(w.d[k]);
+    }
     dfree(w.b);
-    dfree(w.partial);
+    dfree(w.part);
+    dfree(w.part_s);
     dfree(w.scal);
-    dfree(w.counter);
+    if (w.graph) (void)hipGraphExecDestroy(w.graph);
+    if (w.capture) (void)hipStreamDestroy(w.capture);
     if (w.host_scal) (void)hipHostFree(w.host_scal);
     for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
     dfree(d->ops_dev);
@@ -359,22 +363,23 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     }
     DeviceGuard dg(m->device);
     const size_t nv = size_t(m->ne) * d->nphi;
-    const int nb = (int)((m->ne + 127) / 128);
     CgWork& w = d->cg;
-    w.nblocks = nb;
+    const int G = cg_grid(m->ne);
+    w.grid = G;
     hipError_t e = hipMalloc(&d->ops_dev, d->ops_bytes);
     if (e == hipSuccess) e = hipMemcpy(d->ops_dev, d->ops_host, d->ops_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&w.x, nv);
-    if (e == hipSuccess) e = dalloc(&w.r, nv);
-    if (e == hipSuccess) e = dalloc(&w.d[0], nv);
-    if (e == hipSuccess) e = dalloc(&w.d[1], nv);
-    if (e == hipSuccess) e = dalloc(&w.q, nv);
+    for (int k = 0; k < 2; ++k) {
+        if (e == hipSuccess) e = dalloc(&w.r[k], nv);
+        if (e == hipSuccess) e = dalloc(&w.q[k], nv);
+        if (e == hipSuccess) e = dalloc(&w.d[k], nv);
+    }
     if (e == hipSuccess) e = dalloc(&w.b, nv);
-    if (e == hipSuccess) e = dalloc(&w.partial, size_t(2) * nb);
+    if (e == hipSuccess) e = dalloc(&w.part, size_t(8) * G);
+    if (e == hipSuccess) e = dalloc(&w.part_s, size_t(2) * G);
     if (e == hipSuccess) e = dalloc(&w.scal, CgScalars::NSCAL);
-    if (e == hipSuccess) e = dalloc(&w.counter, 4);
-    if (e == hipSuccess) e = hipMemset(w.counter, 0, 4 * sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(w.scal, 0, CgScalars::NSCAL * sizeof(double));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), CgScalars::NSCAL * sizeof(double),
                           hipHostMallocDefault);
@@ -533,35 +538,57 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
     typedef CgScalars S;
     const bool prof = prm->profile != 0;
     const int gb = prm->graph_block;
-    if (prof && (int)w.events.size() < 2 * gb + 1) {
+    if (prof && (int)w.events.size() < gb + 1) {
         for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
-        w.events.assign(2 * gb + 1, nullptr);
+        w.events.assign(gb + 1, nullptr);
         for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
     }
+    if (!prof && (w.graph == nullptr || w.graph_block != gb)) {
+        // capture one block of gb iterations on the private stream
+        if (w.graph) {
+            SLD_HIP_CHECK(hipGraphExecDestroy(w.graph));
+            w.graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        SLD_HIP_CHECK(hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int k = 0; k < gb && ce == hipSuccess; ++k) ce = launch_cg_step(d, k & 1, w.capture);
+        hipError_t ee = hipStreamEndCapture(w.capture, &g);
+        SLD_HIP_CHECK(ce);
+        SLD_HIP_CHECK(ee);
+        hipError_t ie = hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        SLD_HIP_CHECK(ie);
+        w.graph_block = gb;
+    }
     int iters = 0, done = 0, timed = 0;
-    double t_apply = 0, t_update = 0;
+    double t_step = 0;
+    int launched = 0;
     while (true) {
-        if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[0], s));
-        for (int k = 0; k < gb; ++k) {
-            SLD_HIP_CHECK(launch_cg_apply_only(d, k & 1, s));
-            if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[2 * k + 1], s));
-            SLD_HIP_CHECK(launch_cg_update_only(d, k & 1, s));
-            if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[2 * k + 2], s));
+        if (prof) {
+            // iterations launched one by one with an event after each (kernel timing)
+            SLD_HIP_CHECK(hipEventRecord(w.events[0], s));
+            for (int k = 0; k < gb; ++k) {
+                SLD_HIP_CHECK(launch_cg_step(d, k & 1, s));
+                SLD_HIP_CHECK(hipEventRecord(w.events[k + 1], s));
+            }
+        } else {
+            SLD_HIP_CHECK(hipGraphLaunch(w.graph, s));
         }
         SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
                                      hipMemcpyDeviceToHost, s));
         SLD_HIP_CHECK(hipStreamSynchronize(s));
-        const int before = iters;
-        iters = (int)w.host_scal[S::ITER];
         done = (int)w.host_scal[S::DONE];
+        const int before = launched;
+        // launches that did work: the counter of the slot written last
+        launched = (int)std::max(w.host_scal[S::ITER0], w.host_scal[S::ITER1]);
+        iters = done ? (int)w.host_scal[S::ITER] : launched - 1;
         if (prof) {
-            const int nk = iters - before;  // iterations that did work in this block
+            const int nk = launched - before;
             for (int k = 0; k < nk && k < gb; ++k) {
-                float a = 0, u = 0;
-                SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[2 * k], w.events[2 * k + 1]));
-                SLD_HIP_CHECK(hipEventElapsedTime(&u, w.events[2 * k + 1], w.events[2 * k + 2]));
-                t_apply += a;
-                t_update += u;
+                float a = 0;
+                SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[k], w.events[k + 1]));
+                t_step += a;
                 ++timed;
             }
         }
@@ -572,15 +599,14 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
     SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     SLD_HIP_CHECK(hipStreamSynchronize(s));
-    const double rt = w.host_scal[S::FLAG];
+    const double rt = w.host_scal[S::RTRUE];
     if (rep) {
         rep->iters = iters;
         rep->converged = done == 1;
         rep->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
         rep->rel_res_true = bb > 0 ? std::sqrt(rt / bb) : 0.0;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        rep->apply_us = timed ? 1e3 * t_apply / timed : 0.0;
-        rep->update_us = timed ? 1e3 * t_update / timed : 0.0;
+        rep->step_us = timed ? 1e3 * t_step / timed : 0.0;
         rep->timed_iters = timed;
         rep->reserved = 0;
     }

@@ -1,0 +1,285 @@
+// Device helpers shared by the operator and CG kernels (gfx950, wave64).
+//
+// Operator form used on the device (equivalent to eq. pressure_final, derived from the
+// reference factorisation of Section 2.4 and the split dual space of Section 2.2):
+//
+// For triangle i with affine map x = P0 + J xi (eq. linmap), A_i = det J = 2|T_i|,
+// G = J^{-1}, and an edge alpha shared with triangle r:
+//   * the dual mass matrix of the edge is A_i/3 M^L + A_r/3 M^R (eq. MassMatrixD); both
+//     halves carry the main Lagrange basis, so static condensation onto the p+1 shared
+//     edge nodes gives Mhat^{-1} in closed form: the projected gradient on the edge nodes is
+//       x_H = (A_i g_i + A_r g_r)/(A_i + A_r) + 3 |Gamma| n (C delta)/(A_i + A_r),
+//     with g_s = grad p_s at the edge nodes, delta = p_r - p_i at the edge nodes (jump term
+//     of eq. ad5.2, C = S0^{-1} M1), and inside each half ghat = grad p_s + sum_m Delta_m chi_m
+//     with Delta = x_H - g_s;
+//   * the divergence D = -Q^T (Section 2.3) tested with phi_k then gives
+//       (K p)_i = -A_i sum_{de} (G G^T)_{de} S_{de} p_i
+//                 + sum_alpha [ |Gamma| M1 (n . x_H) on the edge nodes
+//                               - A_i sum_d Pt_alpha,d (G Delta)_d ].
+// Everything per element is the two edge vectors of the triangle (32 bytes) and its
+// neighbour table: no per-element operator is stored (Section 2.4.1).
+//
+// Work split: three lanes per triangle, lane alpha owning local edge alpha.  Each lane works
+// in the triangle's frame relabelled so that its edge is local edge 0 (a cyclic renaming of
+// the vertices = a DOF permutation plus new edge vectors), so all lanes run the same code on
+// the same reference matrices (uniform, scalar-cache resident) and only data differ.  The
+// volume term is split by rotation orbits of the nodes: each lane computes the rows of the
+// orbit representatives in its own frame, which together cover every row once.  The three
+// partial rows are combined through LDS in a fixed order (deterministic).
+#pragma once
+
+#include "sld_internal.h"
+
+namespace sld_dev {
+
+constexpr int kTriPerBlock = 64;                 // triangles per block
+constexpr int kBlockTri = 3 * kTriPerBlock;      // 192 threads: three lanes per triangle
+constexpr int kBlockFlat = 256;                  // threads of flat (per-DOF) kernels
+
+template <int P>
+struct Tab {
+    static constexpr int N = (P + 1) * (P + 2) / 2;
+    int na[N] = {}, nb[N] = {};
+    int rot[3][N] = {};     // rot[ar][l]: original index of node l of the frame relabelled by ar
+    int rep[N] = {};        // orbit representatives (rows of the volume term per lane)
+    int nrep = 0;
+    int centre = -1;        // node fixed by the rotation (p divisible by 3), handled by lane 0
+    constexpr Tab() {
+        int k = 0;
+        for (int b = 0; b <= P; ++b)
+            for (int a = 0; a <= P - b; ++a) { na[k] = a; nb[k] = b; ++k; }
+        for (int l = 0; l < N; ++l) {
+            int a = na[l], b = nb[l], c = P - a - b;
+            rot[0][l] = main_idx(P, a, b);
+            rot[1][l] = main_idx(P, c, a);   // v'0 = v1, v'1 = v2, v'2 = v0
+            rot[2][l] = main_idx(P, b, c);   // v'0 = v2, v'1 = v0, v'2 = v1
+        }
+        bool seen[N] = {};
+        for (int l = 0; l < N; ++l) {
+            if (seen[l]) continue;
+            if (rot[1][l] == l) {
+                centre = l;
+                seen[l] = true;
+                continue;
+            }
+            rep[nrep++] = l;
+            seen[rot[0][l]] = seen[rot[1][l]] = seen[rot[2][l]] = true;
+        }
+    }
+};
+
+template <int P>
+__device__ __forceinline__ int rot_sel(int al, int l) {
+    constexpr Tab<P> T{};
+    return al == 0 ? T.rot[0][l] : (al == 1 ? T.rot[1][l] : T.rot[2][l]);
+}
+
+struct Geo {
+    double A;                    // det J = 2 |T|
+    double G00, G01, G10, G11;   // G = J^{-1}, G[d][c] = d xi_d / d x_c
+};
+
+__device__ __forceinline__ Geo make_geo(double e1x, double e1y, double e2x, double e2y) {
+    Geo g;
+    g.A = e1x * e2y - e1y * e2x;
+    const double inv = 1.0 / g.A;
+    g.G00 = e2y * inv;
+    g.G01 = -e2x * inv;
+    g.G10 = -e1y * inv;
+    g.G11 = e1x * inv;
+    return g;
+}
+
+// Edge vectors of a triangle relabelled so that local edge ar becomes edge 0:
+// ar = 0: (e1, e2); ar = 1: (e2 - e1, -e1); ar = 2: (-e2, e1 - e2).
+__device__ __forceinline__ void relabel(double4 e, int ar, double& e1x, double& e1y, double& e2x,
+                                        double& e2y) {
+    const double a1x = e.z - e.x, a1y = e.w - e.y;
+    e1x = ar == 0 ? e.x : (ar == 1 ? a1x : -e.z);
+    e1y = ar == 0 ? e.y : (ar == 1 ? a1y : -e.w);
+    e2x = ar == 0 ? e.z : (ar == 1 ? -e.x : -a1x);
+    e2y = ar == 0 ? e.w : (ar == 1 ? -e.y : -a1y);
+}
+
+__device__ __forceinline__ int pick(int4 v, int al) { return al == 0 ? v.x : (al == 1 ? v.y : v.z); }
+
+// Loaders of a main-grid vector value (t = triangle, l = DOF)
+template <int N>
+struct LoadPlain {
+    const double* __restrict__ src;
+    __device__ __forceinline__ double at(int64_t t, int l) const { return src[t * N + l]; }
+};
+
+// CG direction: r + beta d_old
+template <int N>
+struct LoadDir {
+    const double* __restrict__ r;
+    const double* __restrict__ d;
+    double beta;
+    __device__ __forceinline__ double at(int64_t t, int l) const {
+        return fma(beta, d[t * N + l], r[t * N + l]);
+    }
+};
+
+// Lane `al` of triangle i: contributions to (K p)_i in the frame relabelled by al.
+// pl receives p_i in that frame.  y receives local rows (volume rows of this lane's orbit
+// representatives, plus the full edge-al term).
+template <int P, class L>
+__device__ __forceinline__ void schur_edge_lane(int64_t i, int al, const RefOps<P>& R,
+                                                const double4* __restrict__ geo,
+                                                const int4* __restrict__ nbr, const L& ld,
+                                                double (&pl)[RefOps<P>::NPHI],
+                                                double (&y)[RefOps<P>::NPHI]) {
+    constexpr int N = RefOps<P>::NPHI;
+    constexpr int NE = P + 1;
+    constexpr Tab<P> T{};
+#pragma unroll
+    for (int l = 0; l < N; ++l) pl[l] = ld.at(i, rot_sel<P>(al, l));
+    double e1x, e1y, e2x, e2y;
+    relabel(geo[i], al, e1x, e1y, e2x, e2y);
+    const Geo g = make_geo(e1x, e1y, e2x, e2y);
+    const double m00 = g.G00 * g.G00 + g.G01 * g.G01;
+    const double m01 = g.G00 * g.G10 + g.G01 * g.G11;
+    const double m11 = g.G10 * g.G10 + g.G11 * g.G11;
+#pragma unroll
+    for (int k = 0; k < N; ++k) y[k] = 0.0;
+    // volume term -A (m00 S0 + m01 S1 + m11 S2) p on this lane's rows
+#pragma unroll
+    for (int q = 0; q < T.nrep; ++q) {
+        const int k = T.rep[q];
+        double s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            s0 = fma(R.S[0][k][l], pl[l], s0);
+            s1 = fma(R.S[1][k][l], pl[l], s1);
+            s2 = fma(R.S[2][k][l], pl[l], s2);
+        }
+        y[k] = -g.A * (m00 * s0 + m01 * s1 + m11 * s2);
+    }
+    if (T.centre >= 0 && al == 0) {
+        const int k = T.centre >= 0 ? T.centre : 0;
+        double s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            s0 = fma(R.S[0][k][l], pl[l], s0);
+            s1 = fma(R.S[1][k][l], pl[l], s1);
+            s2 = fma(R.S[2][k][l], pl[l], s2);
+        }
+        y[k] = -g.A * (m00 * s0 + m01 * s1 + m11 * s2);
+    }
+    const int nb = pick(nbr[i], al);
+    const double snx = e1y, sny = -e1x;  // |Gamma| n, outward, of local edge 0
+    if (nb < 0) {
+        // wall edge: no dual coupling; give back this sub-triangle's share of the volume term
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                s0 = fma(R.Sh[0][0][k][l], pl[l], s0);
+                s1 = fma(R.Sh[0][1][k][l], pl[l], s1);
+                s2 = fma(R.Sh[0][2][k][l], pl[l], s2);
+            }
+            y[k] += g.A * (m00 * s0 + m01 * s1 + m11 * s2);
+        }
+        return;
+    }
+    const int64_t r = nb >> 2;
+    const int ar = nb & 3;
+    double pr[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) pr[l] = ld.at(r, rot_sel<P>(ar, l));
+    double f1x, f1y, f2x, f2y;
+    relabel(geo[r], ar, f1x, f1y, f2x, f2y);
+    const Geo gr = make_geo(f1x, f1y, f2x, f2y);
+    const double wsum = 1.0 / (g.A + gr.A);
+    double delta[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) delta[m] = pr[P - m] - pl[m];  // edge-0 nodes are 0..P
+    double gd0[NE], gd1[NE], tn[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        double ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            ds0 = fma(R.E[0][0][m][l], pl[l], ds0);
+            ds1 = fma(R.E[0][1][m][l], pl[l], ds1);
+            dn0 = fma(R.E[0][0][P - m][l], pr[l], dn0);
+            dn1 = fma(R.E[0][1][P - m][l], pr[l], dn1);
+        }
+        const double gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
+        const double gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
+        double cd = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) cd = fma(R.C[m][q], delta[q], cd);
+        const double hx = (g.A * gsx + gr.A * gnx + 3.0 * snx * cd) * wsum;
+        const double hy = (g.A * gsy + gr.A * gny + 3.0 * sny * cd) * wsum;
+        tn[m] = snx * hx + sny * hy;
+        const double dx = hx - gsx, dy = hy - gsy;
+        gd0[m] = g.G00 * dx + g.G01 * dy;
+        gd1[m] = g.G10 * dx + g.G11 * dy;
+    }
+    // line term |Gamma| int phi_k n.x_H on the edge nodes
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        double s = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) s = fma(R.M1[m][q], tn[q], s);
+        y[m] += s;
+    }
+    // sub-triangle correction -A sum_d Pt_d (G Delta)_d
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double s = 0;
+#pragma unroll
+        for (int m = 0; m < NE; ++m) {
+            s = fma(R.Pt[0][0][k][m], gd0[m], s);
+            s = fma(R.Pt[0][1][k][m], gd1[m], s);
+        }
+        y[k] = fma(-g.A, s, y[k]);
+    }
+}
+
+// Scatter a lane's local rows to LDS slot al in natural numbering.
+template <int P>
+__device__ __forceinline__ void lds_scatter(double* slot_base /* [4][N] of this triangle */, int al,
+                                            const double (&y)[RefOps<P>::NPHI]) {
+    constexpr int N = RefOps<P>::NPHI;
+#pragma unroll
+    for (int k = 0; k < N; ++k) slot_base[al * N + rot_sel<P>(al, k)] = y[k];
+}
+
+// Deterministic block sum of NV values; result returned in every thread.
+template <int NV, int NT>
+__device__ __forceinline__ void block_sum_all(double (&v)[NV]) {
+    __shared__ double sh[NV][NT / 64];
+#pragma unroll
+    for (int c = 0; c < NV; ++c)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) sh[c][wid] = v[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double s = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) s += sh[c][w];
+        v[c] = s;
+    }
+}
+
+// Sum of partial[0..n) in a fixed order, identical in every block (n <= a few thousand).
+template <int NT>
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ partial, int n) {
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < n; b += NT) v[0] += partial[b];
+    // the butterfly mixes lanes in a fixed pattern: the same in every block
+    block_sum_all<1, NT>(v);
+    return v[0];
+}
+
+}  // namespace sld_dev

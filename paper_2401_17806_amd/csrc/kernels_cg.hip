@@ -1,0 +1,341 @@
+// Matrix-free conjugate gradients on -K (Section 2.3: the pressure system of eq.
+// pressure_final is symmetric, so CG applies; K itself is negative semi-definite).
+//
+// One iteration = ONE kernel on a fixed grid of G blocks (k_cg_step).  Launch k reads the
+// state (r, q, d)_{k-1} written by launch k-1 (ping-pong buffers by parity) and the G
+// partials of four dot products of launch k-1, and in a single pass over the triangles
+//   alpha_{k-1} = rr_{k-1} / dq_{k-1}
+//   rr_k(rec)   = rr_{k-1} - 2 alpha rq_{k-1} + alpha^2 qq_{k-1}     (one-step recurrence
+//                 from a directly summed rr_{k-1}, so rounding does not accumulate)
+//   beta_{k-1}  = rr_k(rec) / rr_{k-1}
+//   r_k = r_{k-1} - alpha q_{k-1},  d_k = r_k + beta d_{k-1},  x += alpha d_{k-1}
+//   q_k = -K d_k   (neighbours' r_k, d_k are recomputed from their (r, q, d)_{k-1})
+//   partials of rr_k = r_k.r_k, dq_k = d_k.q_k, rq_k = r_k.q_k, qq_k = q_k.q_k.
+// In exact arithmetic this is plain CG (Section 2.3).  Global scalars are never published
+// through in-kernel atomics: every block sums the previous launch's partials itself in a
+// fixed order, so all blocks take bitwise identical decisions and results are deterministic.
+// The iteration counter is double-buffered by parity for the same reason.
+#include "device_common.h"
+
+using namespace sld_dev;
+
+namespace {
+
+typedef CgScalars S;
+
+// r = K x - b_int (true residual of the CG system -K x = -b_int) and its rr partials.
+template <int P>
+__global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restrict__ ops,
+                                                        const double4* __restrict__ geo,
+                                                        const int4* __restrict__ nbr, int64_t ne,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ bint,
+                                                        double* __restrict__ r,
+                                                        double* __restrict__ part_out,
+                                                        const double* __restrict__ scal) {
+    constexpr int N = RefOps<P>::NPHI;
+    if (scal[S::DONE] != 0.0) return;
+    __shared__ double sm[kTriPerBlock][4][N];
+    const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
+    double acc[1] = {0.0};
+    for (int64_t tile = blockIdx.x; tile * kTriPerBlock < ne; tile += gridDim.x) {
+        const int64_t i = tile * kTriPerBlock + tl;
+        const bool valid = i < ne;
+        if (valid) {
+            double pl[N], y[N];
+            LoadPlain<N> ld{x};
+            schur_edge_lane<P>(i, al, *ops, geo, nbr, ld, pl, y);
+            lds_scatter<P>(&sm[tl][0][0], al, y);
+        }
+        __syncthreads();
+        if (valid) {
+            for (int k = al; k < N; k += 3) {
+                const double v = (sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k]) - bint[i * N + k];
+                r[i * N + k] = v;
+                acc[0] = fma(v, v, acc[0]);
+            }
+        }
+        __syncthreads();
+    }
+    block_sum_all<1, kBlockTri>(acc);
+    if (threadIdx.x == 0) part_out[blockIdx.x] = acc[0];
+}
+
+// CG state loader: d_k = r_k + beta d_{k-1} with r_k = r_{k-1} - alpha q_{k-1}
+template <int N>
+struct LoadStep {
+    const double* __restrict__ r;
+    const double* __restrict__ q;
+    const double* __restrict__ d;
+    double alpha, beta;
+    __device__ __forceinline__ double at(int64_t t, int l) const {
+        const int64_t o = t * N + l;
+        return fma(beta, d[o], fma(-alpha, q[o], r[o]));
+    }
+};
+
+template <int P>
+__global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restrict__ ops,
+                                                       const double4* __restrict__ geo,
+                                                       const int4* __restrict__ nbr, int64_t ne,
+                                                       double* __restrict__ x,
+                                                       const double* __restrict__ r_in,
+                                                       const double* __restrict__ q_in,
+                                                       const double* __restrict__ d_in,
+                                                       double* __restrict__ r_out,
+                                                       double* __restrict__ q_out,
+                                                       double* __restrict__ d_out,
+                                                       const double* __restrict__ part_in,
+                                                       double* __restrict__ part_out,
+                                                       double* __restrict__ scal, int parity) {
+    constexpr int N = RefOps<P>::NPHI;
+    if (scal[S::DONE] != 0.0) return;
+    const int G = gridDim.x;
+    const double it = scal[S::ITER0 + parity];
+    double alpha = 0.0, beta = 0.0;
+    if (it > 0.0) {
+        const double rr = reduce_partials<kBlockTri>(part_in, G);
+        const double dq = reduce_partials<kBlockTri>(part_in + G, G);
+        const double rq = reduce_partials<kBlockTri>(part_in + 2 * G, G);
+        const double qq = reduce_partials<kBlockTri>(part_in + 3 * G, G);
+        // every block takes the same decision from the same sums
+        int stop = 0;
+        if (!isfinite(rr)) stop = 3;
+        else if (rr <= scal[S::TOL2]) stop = 1;
+        else if (!(dq > 0.0) || !isfinite(dq)) stop = 3;
+        else if (it > scal[S::MAXIT]) stop = 2;
+        if (stop) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                scal[S::DONE] = (double)stop;
+                scal[S::RR] = rr;
+                scal[S::ITER] = it - 1.0;  // iterations whose update reached x
+            }
+            return;
+        }
+        alpha = rr / dq;
+        const double rr_next = fma(alpha * alpha, qq, fma(-2.0 * alpha, rq, rr));
+        beta = rr_next / rr;
+    }
+    __shared__ double sm[kTriPerBlock][3][N];
+    const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t tile = blockIdx.x; tile * kTriPerBlock < ne; tile += G) {
+        const int64_t i = tile * kTriPerBlock + tl;
+        const bool valid = i < ne;
+        if (valid) {
+            double pl[N], y[N];
+            LoadStep<N> ld{r_in, q_in, d_in, alpha, beta};
+            schur_edge_lane<P>(i, al, *ops, geo, nbr, ld, pl, y);
+#pragma unroll
+            for (int k = 0; k < N; ++k) sm[tl][al][rot_sel<P>(al, k)] = y[k];
+        }
+        __syncthreads();
+        if (valid) {
+            for (int k = al; k < N; k += 3) {
+                const int64_t o = i * N + k;
+                const double dprev = d_in[o];
+                const double rk = fma(-alpha, q_in[o], r_in[o]);
+                const double dk = fma(beta, dprev, rk);
+                const double qk = -(sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k]);
+                x[o] = fma(alpha, dprev, x[o]);
+                r_out[o] = rk;
+                d_out[o] = dk;
+                q_out[o] = qk;
+                acc[0] = fma(rk, rk, acc[0]);
+                acc[1] = fma(dk, qk, acc[1]);
+                acc[2] = fma(rk, qk, acc[2]);
+                acc[3] = fma(qk, qk, acc[3]);
+            }
+        }
+        __syncthreads();
+    }
+    block_sum_all<4, kBlockTri>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) part_out[c * G + blockIdx.x] = acc[c];
+        if (blockIdx.x == 0) scal[S::ITER0 + (1 - parity)] = it + 1.0;
+    }
+}
+
+// ---------------------------------------------------------------- setup and finish
+// partials of sum(b)
+__global__ __launch_bounds__(kBlockFlat) void k_sum_partials(const double* __restrict__ b, int64_t n,
+                                                             double* __restrict__ part) {
+    double acc[1] = {0.0};
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat)
+        acc[0] += b[t];
+    block_sum_all<1, kBlockFlat>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// one block: scal[idx] = scale * sum(part[0..nb))
+__global__ __launch_bounds__(kBlockFlat) void k_scal_reduce(const double* __restrict__ part, int nb,
+                                                            double* __restrict__ scal, int idx,
+                                                            double scale) {
+    const double s = reduce_partials<kBlockFlat>(part, nb);
+    if (threadIdx.x == 0) scal[idx] = scale * s;
+}
+
+// b_int = b - mean; x = 0 (cold) or kept (warm); d0 = q0 = 0; partials of |b_int|^2
+__global__ __launch_bounds__(kBlockFlat) void k_cg_prep(const double* __restrict__ b, int64_t n,
+                                                        double* __restrict__ bint,
+                                                        double* __restrict__ x, int warm,
+                                                        double* __restrict__ d0,
+                                                        double* __restrict__ d1,
+                                                        double* __restrict__ part,
+                                                        const double* __restrict__ scal) {
+    const double mean = scal[S::MEAN];
+    double acc[1] = {0.0};
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        const double v = b[t] - mean;
+        bint[t] = v;
+        if (!warm) x[t] = 0.0;
+        d0[t] = 0.0;
+        d1[t] = 0.0;
+        acc[0] = fma(v, v, acc[0]);
+    }
+    block_sum_all<1, kBlockFlat>(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// one block: BB, TOL2, ITER, DONE, MAXIT
+__global__ __launch_bounds__(kBlockFlat) void k_cg_scal_init(const double* __restrict__ part, int nb,
+                                                             double* __restrict__ scal, double rtol,
+                                                             int maxit) {
+    const double bb = reduce_partials<kBlockFlat>(part, nb);
+    if (threadIdx.x == 0) {
+        scal[S::BB] = bb;
+        scal[S::TOL2] = rtol * rtol * bb;
+        scal[S::ITER] = 0.0;
+        scal[S::ITER0] = 0.0;
+        scal[S::ITER1] = 0.0;
+        scal[S::MAXIT] = (double)maxit;
+        scal[S::RR] = 0.0;
+        scal[S::ZERO] = bb == 0.0 ? 1.0 : 0.0;
+        scal[S::DONE] = bb == 0.0 ? 1.0 : 0.0;
+    }
+}
+
+// partials of |K x - b_int|^2 and int x (gauge), kx = K x
+template <int P>
+__global__ __launch_bounds__(kBlockFlat) void k_finish_partials(const RefOps<P>* __restrict__ ops,
+                                                                const double4* __restrict__ geo,
+                                                                int64_t ne, const double* __restrict__ kx,
+                                                                const double* __restrict__ bint,
+                                                                const double* __restrict__ x,
+                                                                double* __restrict__ part) {
+    constexpr int N = RefOps<P>::NPHI;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; i < ne;
+         i += (int64_t)gridDim.x * kBlockFlat) {
+        const double4 e = geo[i];
+        const double A = e.x * e.w - e.y * e.z;
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const int64_t o = i * N + k;
+            const double t = kx[o] - bint[o];
+            acc[0] = fma(t, t, acc[0]);
+            s = fma(ops->w[k], x[o], s);
+        }
+        acc[1] = fma(A, s, acc[1]);
+    }
+    block_sum_all<2, kBlockFlat>(acc);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc[0];
+        part[gridDim.x + blockIdx.x] = acc[1];
+    }
+}
+
+__global__ __launch_bounds__(kBlockFlat) void k_finish_reduce(const double* __restrict__ part, int nb,
+                                                              double* __restrict__ scal) {
+    const double a = reduce_partials<kBlockFlat>(part, nb);
+    const double b = reduce_partials<kBlockFlat>(part + nb, nb);
+    if (threadIdx.x == 0) {
+        scal[S::RTRUE] = a;
+        scal[S::INTX] = b;
+    }
+}
+
+__global__ __launch_bounds__(kBlockFlat) void k_gauge_out(int64_t n, const double* __restrict__ x,
+                                                          const double* __restrict__ scal,
+                                                          double inv_area, double* __restrict__ out) {
+    const double shift = scal[S::INTX] * inv_area;
+    const bool zero = scal[S::ZERO] != 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat)
+        out[t] = zero ? 0.0 : x[t] - shift;
+}
+
+template <int P>
+const RefOps<P>* ops_of(const sld_disc_s* d) { return reinterpret_cast<const RefOps<P>*>(d->ops_dev); }
+
+#define SLD_DISPATCH(p, CALL)                                   \
+    switch (p) {                                                \
+        case 1: { constexpr int PP = 1; CALL; } break;          \
+        case 2: { constexpr int PP = 2; CALL; } break;          \
+        case 3: { constexpr int PP = 3; CALL; } break;          \
+        case 4: { constexpr int PP = 4; CALL; } break;          \
+        default: return hipErrorInvalidValue;                   \
+    }
+
+}  // namespace
+
+int cg_grid(int64_t ne) {
+    const int64_t tiles = (ne + kTriPerBlock - 1) / kTriPerBlock;
+    return (int)(tiles < kCgMaxGrid ? tiles : kCgMaxGrid);
+}
+
+hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
+                           double rtol, int maxit, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    const CgWork& w = d->cg;
+    const int64_t n = m->ne * d->nphi;
+    const int G = w.grid;
+    hipLaunchKernelGGL(k_sum_partials, dim3(G), dim3(kBlockFlat), 0, s, b, n, w.part_s);
+    hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal,
+                       (int)S::MEAN, 1.0 / (double)n);
+    if (warm) {
+        hipError_t e = hipMemcpyAsync(w.x, p0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_cg_prep, dim3(G), dim3(kBlockFlat), 0, s, b, n, w.b, w.x, warm ? 1 : 0,
+                       w.d[0], w.q[0], w.part_s, w.scal);
+    hipLaunchKernelGGL(k_cg_scal_init, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal, rtol,
+                       maxit);
+    // r_0 = K x - b_int (the residual of -K x = -b_int); q, d of "iteration -1" are zero
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(G), dim3(kBlockTri), 0, s,
+                                          ops_of<PP>(d), m->geo, m->nbr, m->ne, w.x, w.b, w.r[0],
+                                          w.part_s, w.scal));
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    const CgWork& w = d->cg;
+    const int G = w.grid;
+    const int o = 1 - parity;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_step<PP>, dim3(G), dim3(kBlockTri), 0, s,
+                                          ops_of<PP>(d), m->geo, m->nbr, m->ne, w.x, w.r[parity],
+                                          w.q[parity], w.d[parity], w.r[o], w.q[o], w.d[o],
+                                          w.part + parity * 4 * G, w.part + o * 4 * G, w.scal,
+                                          parity));
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    const CgWork& w = d->cg;
+    const int G = w.grid;
+    hipError_t e = launch_schur_apply(d, w.x, w.q[0], 1.0, s);
+    if (e != hipSuccess) return e;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_finish_partials<PP>, dim3(G), dim3(kBlockFlat), 0, s,
+                                          ops_of<PP>(d), m->geo, m->ne, w.q[0], w.b, w.x, w.part_s));
+    hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal);
+    const int64_t n = m->ne * d->nphi;
+    hipLaunchKernelGGL(k_gauge_out, dim3(G), dim3(kBlockFlat), 0, s, n, w.x, w.scal,
+                       1.0 / m->area_total, p_out);
+    return hipGetLastError();
+}

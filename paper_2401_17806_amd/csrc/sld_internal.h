@@ -43,18 +43,22 @@ struct sld_mesh_s {
 };
 
 // Workspace of the CG solver (allocated with the disc).
+constexpr int kCgMaxGrid = 1024;  // blocks of every CG kernel (grid-stride beyond)
 struct CgWork {
     double* x = nullptr;
-    double* r = nullptr;
+    double* r[2] = {nullptr, nullptr};  // ping-pong by iteration parity
+    double* q[2] = {nullptr, nullptr};
     double* d[2] = {nullptr, nullptr};
-    double* q = nullptr;
     double* b = nullptr;           // projected right-hand side
-    double* partial = nullptr;     // per-block partial sums
-    double* scal = nullptr;        // device scalars (see cg kernels)
-    unsigned* counter = nullptr;   // last-block counters
+    double* part = nullptr;        // [2][4][grid] partials of rr, dq, rq, qq (by parity)
+    double* part_s = nullptr;      // [2][grid] partials of setup / finish reductions
+    double* scal = nullptr;        // device scalars (CgScalars)
     double* host_scal = nullptr;   // pinned mirror of scal
-    int nblocks = 0;
+    int grid = 0;                  // blocks of every CG kernel
     std::vector<hipEvent_t> events;  // profiling events (created on first profiled solve)
+    hipStream_t capture = nullptr;   // private stream used to capture the iteration graph
+    hipGraphExec_t graph = nullptr;  // captured block of iterations
+    int graph_block = 0;             // iterations in `graph`
 };
 
 struct sld_disc_s {
@@ -74,15 +78,14 @@ hipError_t launch_gradient(const sld_disc_s* d, const double* p, const double* v
 hipError_t launch_divergence(const sld_disc_s* d, const double* v, double scale, double* out,
                              hipStream_t s);
 
-// CG building blocks (kernels.hip)
+// CG building blocks (kernels_cg.hip)
 struct CgScalars {
-    // layout of CgWork::scal (doubles): see kernels.hip
-    enum { RR = 0, BB = 1, ALPHA = 2, BETA = 3, DQ = 4, TOL2 = 5, ITER = 6, DONE = 7,
-           MAXIT = 8, FLAG = 9, MEAN = 10, NSCAL = 16 };
+    // layout of CgWork::scal (doubles)
+    enum { RR = 0, BB = 1, TOL2 = 2, ITER = 3, DONE = 4, MAXIT = 5, MEAN = 6, ZERO = 7,
+           RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, NSCAL = 16 };
 };
+int cg_grid(int64_t ne);
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
                            double rtol, int maxit, hipStream_t s);
-hipError_t launch_cg_iteration(const sld_disc_s* d, int parity, hipStream_t s);
-hipError_t launch_cg_apply_only(const sld_disc_s* d, int parity, hipStream_t s);
-hipError_t launch_cg_update_only(const sld_disc_s* d, int parity, hipStream_t s);
+hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s);
 hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s);

@@ -33,14 +33,13 @@ _i32 = ctypes.c_int32
 
 class sld_cg_params(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("maxit", _i32), ("warm_start", _i32),
-                ("graph_block", _i32), ("profile", _i32)]
+                ("graph_block", _i32), ("profile", _i32), ("reserved", _i32)]
 
 
 class sld_cg_report(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged", _i32), ("rel_res", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("apply_us", ctypes.c_double), ("update_us", ctypes.c_double),
-                ("timed_iters", _i32), ("reserved", _i32)]
+                ("step_us", ctypes.c_double), ("timed_iters", _i32), ("reserved", _i32)]
 
 
 def _sig(name, args, res=ctypes.c_int):
@@ -264,14 +263,14 @@ class Disc:
                      graph_block=32, profile=False, stream=None):
         p = self._new(self.main_shape) if p is None else p
         prm = sld_cg_params(float(rtol), int(maxit), int(bool(warm_start)), int(graph_block),
-                            int(bool(profile)))
+                            int(bool(profile)), 0)
         rep = sld_cg_report()
         st = _lib.sld_cg_solve(self.handle, self._dev(b, self.main_shape, "b"),
                                self._dev(p, self.main_shape, "p"), ctypes.byref(prm),
                                ctypes.byref(rep), self._stream(stream))
         report = {"iters": rep.iters, "converged": bool(rep.converged), "rel_res": rep.rel_res,
                   "rel_res_true": rep.rel_res_true, "seconds": rep.seconds,
-                  "apply_us": rep.apply_us, "update_us": rep.update_us,
+                  "step_us": rep.step_us,
                   "timed_iters": rep.timed_iters, "status": STATUS.get(st, st)}
         if st not in (0, 5):
             _check(st)
