@@ -43,6 +43,8 @@ void free_mesh(sld_mesh_s* m) {
     dfree(m->nbr);
     dfree(m->edges);
     dfree(m->tedges);
+    dfree(m->halo_off);
+    dfree(m->halo_ids);
     delete m;
 }
 
@@ -275,6 +277,47 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
                 }
             }
         }
+        // tiles of kTriPerBlock consecutive triangles: halo lists and tile-local slots
+        const int64_t ntiles = (ne + kTriPerBlock - 1) / kTriPerBlock;
+        std::vector<int> halo_off(ntiles + 1, 0), halo_ids;
+        halo_ids.reserve(size_t(ne));
+        for (int64_t t = 0; t < ntiles; ++t) {
+            const int64_t i0 = t * kTriPerBlock, i1 = std::min<int64_t>(ne, i0 + kTriPerBlock);
+            std::vector<int> ext;
+            for (int64_t i = i0; i < i1; ++i)
+                for (int al = 0; al < 3; ++al) {
+                    const int nb = al == 0 ? nbr[i].x : (al == 1 ? nbr[i].y : nbr[i].z);
+                    if (nb < 0) continue;
+                    const int r = nb >> 2;
+                    if (r < i0 || r >= i1) ext.push_back(r);
+                }
+            std::sort(ext.begin(), ext.end());
+            ext.erase(std::unique(ext.begin(), ext.end()), ext.end());
+            if ((int)ext.size() + kTriPerBlock >= kSlotWall) {
+                free_mesh(m);
+                sld_set_error("sld_mesh_create: a tile's halo is too large");
+                return SLD_E_MESH;
+            }
+            for (int64_t i = i0; i < i1; ++i) {
+                int slots[3];
+                for (int al = 0; al < 3; ++al) {
+                    const int nb = al == 0 ? nbr[i].x : (al == 1 ? nbr[i].y : nbr[i].z);
+                    if (nb < 0) {
+                        slots[al] = kSlotWall;
+                        continue;
+                    }
+                    const int r = nb >> 2;
+                    if (r >= i0 && r < i1) slots[al] = int(r - i0);
+                    else
+                        slots[al] = kTriPerBlock +
+                                    int(std::lower_bound(ext.begin(), ext.end(), r) - ext.begin());
+                }
+                nbr[i].w = slots[0] | (slots[1] << 10) | (slots[2] << 20);
+            }
+            m->hmax = std::max<int>(m->hmax, (int)ext.size());
+            halo_ids.insert(halo_ids.end(), ext.begin(), ext.end());
+            halo_off[t + 1] = (int)halo_ids.size();
+        }
         if (device == -1) {
             *out = m;  // host-only handle: tables and node queries, no device work
             return SLD_OK;
@@ -290,6 +333,14 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
         if (e == hipSuccess) e = dalloc(&m->nbr, ne);
         if (e == hipSuccess) e = dalloc(&m->tedges, ne);
         if (e == hipSuccess) e = dalloc(&m->edges, m->nd);
+        if (e == hipSuccess) e = dalloc(&m->halo_off, halo_off.size());
+        if (e == hipSuccess) e = dalloc(&m->halo_ids, halo_ids.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(m->halo_off, halo_off.data(), sizeof(int) * halo_off.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess && !halo_ids.empty())
+            e = hipMemcpy(m->halo_ids, halo_ids.data(), sizeof(int) * halo_ids.size(),
+                          hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(m->geo, geo.data(), sizeof(double4) * ne, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(m->nbr, nbr.data(), sizeof(int4) * ne, hipMemcpyHostToDevice);
         if (e == hipSuccess)

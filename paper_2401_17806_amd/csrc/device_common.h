@@ -32,7 +32,6 @@
 
 namespace sld_dev {
 
-constexpr int kTriPerBlock = 64;                 // triangles per block
 constexpr int kBlockTri = 3 * kTriPerBlock;      // 192 threads: three lanes per triangle
 constexpr int kBlockFlat = 256;                  // threads of flat (per-DOF) kernels
 
@@ -121,22 +120,22 @@ struct LoadDir {
     }
 };
 
-// Lane `al` of triangle i: contributions to (K p)_i in the frame relabelled by al.
-// pl receives p_i in that frame.  y receives local rows (volume rows of this lane's orbit
-// representatives, plus the full edge-al term).
-template <int P, class L>
-__device__ __forceinline__ void schur_edge_lane(int64_t i, int al, const RefOps<P>& R,
-                                                const double4* __restrict__ geo,
-                                                const int4* __restrict__ nbr, const L& ld,
-                                                double (&pl)[RefOps<P>::NPHI],
-                                                double (&y)[RefOps<P>::NPHI]) {
+// Core of lane `al` of a triangle: contributions to (K p)_i in the frame relabelled by al.
+// pl holds p_i in that frame, pr the neighbour's DOFs in the neighbour's frame relabelled by
+// ar (its shared edge is its local edge 0); e / er are the two triangles' edge vectors; nb < 0
+// marks a wall edge.  y receives local rows: this lane's volume rows (orbit representatives)
+// plus the full edge-al term.
+template <int P>
+__device__ __forceinline__ void edge_lane_core(int al, const RefOps<P>& R, double4 e, int nb,
+                                               int ar, double4 er,
+                                               const double (&pl)[RefOps<P>::NPHI],
+                                               const double (&pr)[RefOps<P>::NPHI],
+                                               double (&y)[RefOps<P>::NPHI]) {
     constexpr int N = RefOps<P>::NPHI;
     constexpr int NE = P + 1;
     constexpr Tab<P> T{};
-#pragma unroll
-    for (int l = 0; l < N; ++l) pl[l] = ld.at(i, rot_sel<P>(al, l));
     double e1x, e1y, e2x, e2y;
-    relabel(geo[i], al, e1x, e1y, e2x, e2y);
+    relabel(e, al, e1x, e1y, e2x, e2y);
     const Geo g = make_geo(e1x, e1y, e2x, e2y);
     const double m00 = g.G00 * g.G00 + g.G01 * g.G01;
     const double m01 = g.G00 * g.G10 + g.G01 * g.G11;
@@ -167,7 +166,6 @@ __device__ __forceinline__ void schur_edge_lane(int64_t i, int al, const RefOps<
         }
         y[k] = -g.A * (m00 * s0 + m01 * s1 + m11 * s2);
     }
-    const int nb = pick(nbr[i], al);
     const double snx = e1y, sny = -e1x;  // |Gamma| n, outward, of local edge 0
     if (nb < 0) {
         // wall edge: no dual coupling; give back this sub-triangle's share of the volume term
@@ -184,13 +182,8 @@ __device__ __forceinline__ void schur_edge_lane(int64_t i, int al, const RefOps<
         }
         return;
     }
-    const int64_t r = nb >> 2;
-    const int ar = nb & 3;
-    double pr[N];
-#pragma unroll
-    for (int l = 0; l < N; ++l) pr[l] = ld.at(r, rot_sel<P>(ar, l));
     double f1x, f1y, f2x, f2y;
-    relabel(geo[r], ar, f1x, f1y, f2x, f2y);
+    relabel(er, ar, f1x, f1y, f2x, f2y);
     const Geo gr = make_geo(f1x, f1y, f2x, f2y);
     const double wsum = 1.0 / (g.A + gr.A);
     double delta[NE];
@@ -238,6 +231,33 @@ __device__ __forceinline__ void schur_edge_lane(int64_t i, int al, const RefOps<
         }
         y[k] = fma(-g.A, s, y[k]);
     }
+}
+
+// Lane `al` of triangle i with p read through a loader (global memory).
+template <int P, class L>
+__device__ __forceinline__ void schur_edge_lane(int64_t i, int al, const RefOps<P>& R,
+                                                const double4* __restrict__ geo,
+                                                const int4* __restrict__ nbr, const L& ld,
+                                                double (&pl)[RefOps<P>::NPHI],
+                                                double (&y)[RefOps<P>::NPHI]) {
+    constexpr int N = RefOps<P>::NPHI;
+#pragma unroll
+    for (int l = 0; l < N; ++l) pl[l] = ld.at(i, rot_sel<P>(al, l));
+    const int nb = pick(nbr[i], al);
+    double pr[N];
+    double4 er = make_double4(0, 0, 0, 0);
+    int ar = 0;
+    if (nb >= 0) {
+        const int64_t r = nb >> 2;
+        ar = nb & 3;
+#pragma unroll
+        for (int l = 0; l < N; ++l) pr[l] = ld.at(r, rot_sel<P>(ar, l));
+        er = geo[r];
+    } else {
+#pragma unroll
+        for (int l = 0; l < N; ++l) pr[l] = 0.0;
+    }
+    edge_lane_core<P>(al, R, geo[i], nb, ar, er, pl, pr, y);
 }
 
 // Scatter a lane's local rows to LDS slot al in natural numbering.

@@ -61,24 +61,20 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
     if (threadIdx.x == 0) part_out[blockIdx.x] = acc[0];
 }
 
-// CG state loader: d_k = r_k + beta d_{k-1} with r_k = r_{k-1} - alpha q_{k-1}
-template <int N>
-struct LoadStep {
-    const double* __restrict__ r;
-    const double* __restrict__ q;
-    const double* __restrict__ d;
-    double alpha, beta;
-    __device__ __forceinline__ double at(int64_t t, int l) const {
-        const int64_t o = t * N + l;
-        return fma(beta, d[o], fma(-alpha, q[o], r[o]));
-    }
-};
+// Dynamic LDS of k_cg_step, in doubles: sd [(T + hmax) N] directions d_k of the tile then of
+// its halo; sr [T N] residuals r_k of the tile; sm [T][3][N] per-lane partial rows.
+inline size_t step_lds_bytes(int nphi, int hmax) {
+    return sizeof(double) * (size_t)nphi * (size_t)(kTriPerBlock + hmax + kTriPerBlock +
+                                                    3 * kTriPerBlock);
+}
 
 template <int P>
 __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restrict__ ops,
                                                        const double4* __restrict__ geo,
-                                                       const int4* __restrict__ nbr, int64_t ne,
-                                                       double* __restrict__ x,
+                                                       const int4* __restrict__ nbr,
+                                                       const int* __restrict__ halo_off,
+                                                       const int* __restrict__ halo_ids, int hmax,
+                                                       int64_t ne, double* __restrict__ x,
                                                        const double* __restrict__ r_in,
                                                        const double* __restrict__ q_in,
                                                        const double* __restrict__ d_in,
@@ -89,15 +85,22 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restri
                                                        double* __restrict__ part_out,
                                                        double* __restrict__ scal, int parity) {
     constexpr int N = RefOps<P>::NPHI;
+    constexpr int T = kTriPerBlock;
+    extern __shared__ double lds[];
+    double* sd = lds;
+    double* sr = lds + (size_t)(T + hmax) * N;
+    double* sm = sr + (size_t)T * N;
     if (scal[S::DONE] != 0.0) return;
     const int G = gridDim.x;
     const double it = scal[S::ITER0 + parity];
     double alpha = 0.0, beta = 0.0;
     if (it > 0.0) {
-        const double rr = reduce_partials<kBlockTri>(part_in, G);
-        const double dq = reduce_partials<kBlockTri>(part_in + G, G);
-        const double rq = reduce_partials<kBlockTri>(part_in + 2 * G, G);
-        const double qq = reduce_partials<kBlockTri>(part_in + 3 * G, G);
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = threadIdx.x; b < G; b += kBlockTri)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] += part_in[c * G + b];
+        block_sum_all<4, kBlockTri>(v);
+        const double rr = v[0], dq = v[1], rq = v[2], qq = v[3];
         // every block takes the same decision from the same sums
         int stop = 0;
         if (!isfinite(rr)) stop = 3;
@@ -116,36 +119,67 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restri
         const double rr_next = fma(alpha * alpha, qq, fma(-2.0 * alpha, rq, rr));
         beta = rr_next / rr;
     }
-    __shared__ double sm[kTriPerBlock][3][N];
     const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t tile = blockIdx.x; tile * kTriPerBlock < ne; tile += G) {
-        const int64_t i = tile * kTriPerBlock + tl;
-        const bool valid = i < ne;
-        if (valid) {
-            double pl[N], y[N];
-            LoadStep<N> ld{r_in, q_in, d_in, alpha, beta};
-            schur_edge_lane<P>(i, al, *ops, geo, nbr, ld, pl, y);
-#pragma unroll
-            for (int k = 0; k < N; ++k) sm[tl][al][rot_sel<P>(al, k)] = y[k];
+    for (int64_t tile = blockIdx.x; tile * T < ne; tile += G) {
+        const int64_t i0 = tile * T;
+        const int nown = (int)((ne - i0) < T ? (ne - i0) : T) * N;
+        const int64_t base = i0 * N;
+        // phase 1: state update of the tile (coalesced) and directions of tile + halo into LDS
+        for (int f = threadIdx.x; f < nown; f += kBlockTri) {
+            const int64_t o = base + f;
+            const double dprev = d_in[o];
+            const double rk = fma(-alpha, q_in[o], r_in[o]);
+            const double dk = fma(beta, dprev, rk);
+            x[o] = fma(alpha, dprev, x[o]);
+            r_out[o] = rk;
+            d_out[o] = dk;
+            sd[f] = dk;
+            sr[f] = rk;
+            acc[0] = fma(rk, rk, acc[0]);
+        }
+        const int h0 = halo_off[tile];
+        const int nh = (halo_off[tile + 1] - h0) * N;
+        for (int e = threadIdx.x; e < nh; e += kBlockTri) {
+            const int t = e / N;
+            const int64_t o = (int64_t)halo_ids[h0 + t] * N + (e - t * N);
+            sd[T * N + e] = fma(beta, d_in[o], fma(-alpha, q_in[o], r_in[o]));
         }
         __syncthreads();
-        if (valid) {
-            for (int k = al; k < N; k += 3) {
-                const int64_t o = i * N + k;
-                const double dprev = d_in[o];
-                const double rk = fma(-alpha, q_in[o], r_in[o]);
-                const double dk = fma(beta, dprev, rk);
-                const double qk = -(sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k]);
-                x[o] = fma(alpha, dprev, x[o]);
-                r_out[o] = rk;
-                d_out[o] = dk;
-                q_out[o] = qk;
-                acc[0] = fma(rk, rk, acc[0]);
-                acc[1] = fma(dk, qk, acc[1]);
-                acc[2] = fma(rk, qk, acc[2]);
-                acc[3] = fma(qk, qk, acc[3]);
+        // phase 2: three lanes per triangle, operands from LDS
+        const int64_t i = i0 + tl;
+        if (i < ne) {
+            const int4 nb4 = nbr[i];
+            const int nb = pick(nb4, al);
+            const int slot = (nb4.w >> (10 * al)) & 1023;
+            double pl[N], pr[N], y[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) pl[l] = sd[tl * N + rot_sel<P>(al, l)];
+            int ar = 0;
+            double4 er = make_double4(0, 0, 0, 0);
+            if (nb >= 0) {
+                ar = nb & 3;
+#pragma unroll
+                for (int l = 0; l < N; ++l) pr[l] = sd[slot * N + rot_sel<P>(ar, l)];
+                er = geo[nb >> 2];
+            } else {
+#pragma unroll
+                for (int l = 0; l < N; ++l) pr[l] = 0.0;
             }
+            edge_lane_core<P>(al, *ops, geo[i], nb, ar, er, pl, pr, y);
+#pragma unroll
+            for (int k = 0; k < N; ++k) sm[(tl * 3 + al) * N + rot_sel<P>(al, k)] = y[k];
+        }
+        __syncthreads();
+        // phase 3: q_k = -K d_k (coalesced) and the dot products
+        for (int f = threadIdx.x; f < nown; f += kBlockTri) {
+            const int t = f / N, k = f - t * N;
+            const double qk = -(sm[(t * 3) * N + k] + sm[(t * 3 + 1) * N + k] + sm[(t * 3 + 2) * N + k]);
+            q_out[base + f] = qk;
+            const double dk = sd[f], rk = sr[f];
+            acc[1] = fma(dk, qk, acc[1]);
+            acc[2] = fma(rk, qk, acc[2]);
+            acc[3] = fma(qk, qk, acc[3]);
         }
         __syncthreads();
     }
@@ -317,9 +351,11 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
     const CgWork& w = d->cg;
     const int G = w.grid;
     const int o = 1 - parity;
-    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_step<PP>, dim3(G), dim3(kBlockTri), 0, s,
-                                          ops_of<PP>(d), m->geo, m->nbr, m->ne, w.x, w.r[parity],
-                                          w.q[parity], w.d[parity], w.r[o], w.q[o], w.d[o],
+    const size_t lds = step_lds_bytes(d->nphi, m->hmax);
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_step<PP>, dim3(G), dim3(kBlockTri), lds, s,
+                                          ops_of<PP>(d), m->geo, m->nbr, m->halo_off, m->halo_ids,
+                                          m->hmax, m->ne, w.x, w.r[parity], w.q[parity],
+                                          w.d[parity], w.r[o], w.q[o], w.d[o],
                                           w.part + parity * 4 * G, w.part + o * 4 * G, w.scal,
                                           parity));
     return hipGetLastError();

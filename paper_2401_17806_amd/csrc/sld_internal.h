@@ -22,6 +22,11 @@ void sld_set_error(const std::string& msg);
         }                                                                                \
     } while (0)
 
+// Triangles per tile: one thread block of the apply kernels owns a tile of consecutive
+// triangles; the host builds each tile's halo (its neighbours outside the tile).
+constexpr int kTriPerBlock = 64;
+constexpr int kSlotWall = 1023;  // tile-local slot of a wall neighbour
+
 // Neighbour entry packing: (triangle << 2) | local edge in that triangle; -1 = wall.
 inline int32_t pack_nbr(int32_t tri, int32_t alpha) { return tri < 0 ? -1 : (tri << 2) | alpha; }
 
@@ -36,7 +41,11 @@ struct sld_mesh_s {
     std::vector<double> shift;     // [nd][2] r's frame minus l's frame
     // device
     double4* geo = nullptr;        // [ne] (e1x, e1y, e2x, e2y): e1 = P1-P0, e2 = P2-P0
-    int4* nbr = nullptr;           // [ne] packed neighbour across local edges 0,1,2; w unused
+    int4* nbr = nullptr;           // [ne] packed neighbour across local edges 0,1,2; w = the three
+                                   // tile-local slots (10 bits each): 0..63 own tile, 64+h halo
+    int* halo_off = nullptr;       // [ntiles + 1] offsets into halo_ids
+    int* halo_ids = nullptr;       // halo triangles of every tile, sorted per tile
+    int hmax = 0;                  // largest halo
     int4* edges = nullptr;         // [nd] (l, r, alpha_l, alpha_r)
     int4* tedges = nullptr;        // [ne] (2*j + beta) per local edge; beta = 1 if i = r(j)
     double area_total = 0;         // |Omega|
