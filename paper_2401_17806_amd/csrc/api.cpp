@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -45,6 +46,9 @@ void free_mesh(sld_mesh_s* m) {
     dfree(m->tedges);
     dfree(m->halo_off);
     dfree(m->halo_ids);
+    dfree(m->perm);
+    dfree(m->geo_i);
+    dfree(m->nbr_i);
     delete m;
 }
 
@@ -277,7 +281,51 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
                 }
             }
         }
-        // tiles of kTriPerBlock consecutive triangles: halo lists and tile-local slots
+        // internal order: Morton curve over (periodically wrapped) centroids
+        std::vector<int> perm(ne), inv(ne);
+        {
+            double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+            std::vector<double> cx(ne), cy(ne);
+            for (int64_t i = 0; i < ne; ++i) {
+                double c[2];
+                for (int k = 0; k < 2; ++k) {
+                    c[k] = (m->P[6 * i + k] + m->P[6 * i + 2 + k] + m->P[6 * i + 4 + k]) / 3.0;
+                    if (period) c[k] -= period[k] * std::floor(c[k] / period[k]);
+                    lo[k] = std::min(lo[k], c[k]);
+                    hi[k] = std::max(hi[k], c[k]);
+                }
+                cx[i] = c[0];
+                cy[i] = c[1];
+            }
+            std::vector<std::pair<uint32_t, int>> key(ne);
+            for (int64_t i = 0; i < ne; ++i) {
+                uint32_t q[2];
+                const double c[2] = {cx[i], cy[i]};
+                for (int k = 0; k < 2; ++k) {
+                    const double span = hi[k] > lo[k] ? hi[k] - lo[k] : 1.0;
+                    q[k] = (uint32_t)std::min(65535.0, std::floor((c[k] - lo[k]) / span * 65536.0));
+                }
+                uint32_t code = 0;
+                for (int bit = 0; bit < 16; ++bit)
+                    code |= ((q[0] >> bit) & 1u) << (2 * bit) | ((q[1] >> bit) & 1u) << (2 * bit + 1);
+                key[i] = {code, (int)i};
+            }
+            std::sort(key.begin(), key.end());
+            for (int64_t i = 0; i < ne; ++i) {
+                perm[i] = key[i].second;
+                inv[key[i].second] = (int)i;
+            }
+        }
+        std::vector<double4> geo_i(ne);
+        std::vector<int4> nbr_i(ne);
+        for (int64_t i = 0; i < ne; ++i) {
+            const int c = perm[i];
+            geo_i[i] = geo[c];
+            int v[3] = {nbr[c].x, nbr[c].y, nbr[c].z};
+            for (int al = 0; al < 3; ++al) v[al] = v[al] < 0 ? -1 : pack_nbr(inv[v[al] >> 2], v[al] & 3);
+            nbr_i[i] = make_int4(v[0], v[1], v[2], 0);
+        }
+        // tiles of kTriPerBlock consecutive (internal) triangles: halo lists and local slots
         const int64_t ntiles = (ne + kTriPerBlock - 1) / kTriPerBlock;
         std::vector<int> halo_off(ntiles + 1, 0), halo_ids;
         halo_ids.reserve(size_t(ne));
@@ -286,7 +334,7 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
             std::vector<int> ext;
             for (int64_t i = i0; i < i1; ++i)
                 for (int al = 0; al < 3; ++al) {
-                    const int nb = al == 0 ? nbr[i].x : (al == 1 ? nbr[i].y : nbr[i].z);
+                    const int nb = al == 0 ? nbr_i[i].x : (al == 1 ? nbr_i[i].y : nbr_i[i].z);
                     if (nb < 0) continue;
                     const int r = nb >> 2;
                     if (r < i0 || r >= i1) ext.push_back(r);
@@ -301,7 +349,7 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
             for (int64_t i = i0; i < i1; ++i) {
                 int slots[3];
                 for (int al = 0; al < 3; ++al) {
-                    const int nb = al == 0 ? nbr[i].x : (al == 1 ? nbr[i].y : nbr[i].z);
+                    const int nb = al == 0 ? nbr_i[i].x : (al == 1 ? nbr_i[i].y : nbr_i[i].z);
                     if (nb < 0) {
                         slots[al] = kSlotWall;
                         continue;
@@ -312,12 +360,13 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
                         slots[al] = kTriPerBlock +
                                     int(std::lower_bound(ext.begin(), ext.end(), r) - ext.begin());
                 }
-                nbr[i].w = slots[0] | (slots[1] << 10) | (slots[2] << 20);
+                nbr_i[i].w = slots[0] | (slots[1] << 10) | (slots[2] << 20);
             }
             m->hmax = std::max<int>(m->hmax, (int)ext.size());
             halo_ids.insert(halo_ids.end(), ext.begin(), ext.end());
             halo_off[t + 1] = (int)halo_ids.size();
         }
+        m->halo_total = (int64_t)halo_ids.size();
         if (device == -1) {
             *out = m;  // host-only handle: tables and node queries, no device work
             return SLD_OK;
@@ -333,6 +382,14 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
         if (e == hipSuccess) e = dalloc(&m->nbr, ne);
         if (e == hipSuccess) e = dalloc(&m->tedges, ne);
         if (e == hipSuccess) e = dalloc(&m->edges, m->nd);
+        if (e == hipSuccess) e = dalloc(&m->perm, ne);
+        if (e == hipSuccess) e = dalloc(&m->geo_i, ne);
+        if (e == hipSuccess) e = dalloc(&m->nbr_i, ne);
+        if (e == hipSuccess) e = hipMemcpy(m->perm, perm.data(), sizeof(int) * ne, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(m->geo_i, geo_i.data(), sizeof(double4) * ne, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(m->nbr_i, nbr_i.data(), sizeof(int4) * ne, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = dalloc(&m->halo_off, halo_off.size());
         if (e == hipSuccess) e = dalloc(&m->halo_ids, halo_ids.size());
         if (e == hipSuccess)
@@ -415,7 +472,15 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     DeviceGuard dg(m->device);
     const size_t nv = size_t(m->ne) * d->nphi;
     CgWork& w = d->cg;
-    const int G = cg_grid(m->ne);
+    const char* force = std::getenv("SLD_CG_KERNEL");  // debugging aid: "wave" or "lanes"
+    w.wave_kernel = m->ne >= kWaveKernelMinTri;
+    if (force && std::strcmp(force, "wave") == 0) w.wave_kernel = true;
+    if (force && std::strcmp(force, "lanes") == 0) w.wave_kernel = false;
+    int G = cg_grid_for(m->ne, w.wave_kernel);
+    if (const char* gcap = std::getenv("SLD_CG_GRID")) {  // debugging aid: grid size cap
+        const int cap = std::atoi(gcap);
+        if (cap > 0 && cap < G) G = cap;
+    }
     w.grid = G;
     hipError_t e = hipMalloc(&d->ops_dev, d->ops_bytes);
     if (e == hipSuccess) e = hipMemcpy(d->ops_dev, d->ops_host, d->ops_bytes, hipMemcpyHostToDevice);

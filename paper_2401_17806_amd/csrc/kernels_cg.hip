@@ -191,6 +191,137 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restri
     }
 }
 
+// Large meshes: one wave per tile, one lane per triangle (all three edges in the lane), so
+// waves of a CU progress independently (no block barrier inside the tile loop) and hide each
+// other's memory latency.  Per wave LDS: (T + hmax) N doubles of directions (tile, halo).
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlockWave = 64 * kWavesPerBlock;
+
+inline size_t wave_lds_bytes(int nphi, int hmax) {
+    return sizeof(double) * (size_t)nphi * (size_t)(kTriPerBlock + hmax) * kWavesPerBlock;
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlockWave) void k_cg_step_wave(
+    const RefOps<P>* __restrict__ ops, const double4* __restrict__ geo,
+    const int4* __restrict__ nbr, const int* __restrict__ halo_off,
+    const int* __restrict__ halo_ids, int hmax, int64_t ne, double* __restrict__ x,
+    const double* __restrict__ r_in, const double* __restrict__ q_in,
+    const double* __restrict__ d_in, double* __restrict__ r_out, double* __restrict__ q_out,
+    double* __restrict__ d_out, const double* __restrict__ part_in, double* __restrict__ part_out,
+    double* __restrict__ scal, int parity) {
+    constexpr int N = RefOps<P>::NPHI;
+    constexpr int T = kTriPerBlock;
+    static_assert(T == 64, "one lane per triangle of a tile");
+    extern __shared__ double lds[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* sd = lds + (size_t)wave * (T + hmax) * N;
+    if (scal[S::DONE] != 0.0) return;
+    const int G = gridDim.x;
+    const double it = scal[S::ITER0 + parity];
+    double alpha = 0.0, beta = 0.0;
+    if (it > 0.0) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = threadIdx.x; b < G; b += kBlockWave)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] += part_in[c * G + b];
+        block_sum_all<4, kBlockWave>(v);
+        const double rr = v[0], dq = v[1], rq = v[2], qq = v[3];
+        int stop = 0;
+        if (!isfinite(rr)) stop = 3;
+        else if (rr <= scal[S::TOL2]) stop = 1;
+        else if (!(dq > 0.0) || !isfinite(dq)) stop = 3;
+        else if (it > scal[S::MAXIT]) stop = 2;
+        if (stop) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                scal[S::DONE] = (double)stop;
+                scal[S::RR] = rr;
+                scal[S::ITER] = it - 1.0;
+            }
+            return;
+        }
+        alpha = rr / dq;
+        const double rr_next = fma(alpha * alpha, qq, fma(-2.0 * alpha, rq, rr));
+        beta = rr_next / rr;
+    }
+    const RefOps<P>& R = *ops;
+    const int64_t ntiles = (ne + T - 1) / T;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave; tile < ntiles;
+         tile += (int64_t)G * kWavesPerBlock) {
+        const int64_t i = tile * T + lane;
+        const bool valid = i < ne;
+        double dk[N], rk[N];
+        if (valid) {
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                const int64_t o = i * N + l;
+                const double dprev = d_in[o];
+                rk[l] = fma(-alpha, q_in[o], r_in[o]);
+                dk[l] = fma(beta, dprev, rk[l]);
+                x[o] = fma(alpha, dprev, x[o]);
+                r_out[o] = rk[l];
+                d_out[o] = dk[l];
+                sd[lane * N + l] = dk[l];
+                acc[0] = fma(rk[l], rk[l], acc[0]);
+            }
+        }
+        const int h0 = halo_off[tile];
+        const int nh = (halo_off[tile + 1] - h0) * N;
+        for (int e = lane; e < nh; e += 64) {
+            const int t = e / N;
+            const int64_t o = (int64_t)halo_ids[h0 + t] * N + (e - t * N);
+            sd[T * N + e] = fma(beta, d_in[o], fma(-alpha, q_in[o], r_in[o]));
+        }
+        wave_lds_fence();
+        if (valid) {
+            const double4 e = geo[i];
+            const Geo g = make_geo(e.x, e.y, e.z, e.w);
+            const double m00 = g.G00 * g.G00 + g.G01 * g.G01;
+            const double m01 = g.G00 * g.G10 + g.G01 * g.G11;
+            const double m11 = g.G10 * g.G10 + g.G11 * g.G11;
+            double y[N];
+            volume_term<P>(R, g.A, m00, m01, m11, dk, y);
+            const int4 nb4 = nbr[i];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                const int nb = al == 0 ? nb4.x : (al == 1 ? nb4.y : nb4.z);
+                const int slot = (nb4.w >> (10 * al)) & 1023;
+                double pr[N];
+                int ar = 0;
+                double4 er = make_double4(0, 0, 0, 0);
+                if (nb >= 0) {
+                    ar = nb & 3;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) pr[l] = sd[slot * N + rot_sel<P>(ar, l)];
+                    er = geo[nb >> 2];
+                } else {
+#pragma unroll
+                    for (int l = 0; l < N; ++l) pr[l] = 0.0;
+                }
+                if (al == 0) edge_term<P, 0>(R, g, e, m00, m01, m11, nb, ar, er, dk, pr, y);
+                else if (al == 1) edge_term<P, 1>(R, g, e, m00, m01, m11, nb, ar, er, dk, pr, y);
+                else edge_term<P, 2>(R, g, e, m00, m01, m11, nb, ar, er, dk, pr, y);
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const double qk = -y[k];
+                q_out[i * N + k] = qk;
+                acc[1] = fma(dk[k], qk, acc[1]);
+                acc[2] = fma(rk[k], qk, acc[2]);
+                acc[3] = fma(qk, qk, acc[3]);
+            }
+        }
+        wave_lds_fence();
+    }
+    block_sum_all<4, kBlockWave>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) part_out[c * G + blockIdx.x] = acc[c];
+        if (blockIdx.x == 0) scal[S::ITER0 + (1 - parity)] = it + 1.0;
+    }
+}
+
 // ---------------------------------------------------------------- setup and finish
 // partials of sum(b)
 __global__ __launch_bounds__(kBlockFlat) void k_sum_partials(const double* __restrict__ b, int64_t n,
@@ -211,9 +342,12 @@ __global__ __launch_bounds__(kBlockFlat) void k_scal_reduce(const double* __rest
     if (threadIdx.x == 0) scal[idx] = scale * s;
 }
 
-// b_int = b - mean; x = 0 (cold) or kept (warm); d0 = q0 = 0; partials of |b_int|^2
-__global__ __launch_bounds__(kBlockFlat) void k_cg_prep(const double* __restrict__ b, int64_t n,
-                                                        double* __restrict__ bint,
+// b_int = b - mean in internal order (gathered through perm); x = 0 (cold) or the gathered
+// initial guess (warm); d0 = q0 = 0; partials of |b_int|^2
+__global__ __launch_bounds__(kBlockFlat) void k_cg_prep(const double* __restrict__ b,
+                                                        const double* __restrict__ p0,
+                                                        const int* __restrict__ perm, int nphi,
+                                                        int64_t n, double* __restrict__ bint,
                                                         double* __restrict__ x, int warm,
                                                         double* __restrict__ d0,
                                                         double* __restrict__ d1,
@@ -223,9 +357,11 @@ __global__ __launch_bounds__(kBlockFlat) void k_cg_prep(const double* __restrict
     double acc[1] = {0.0};
     for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * kBlockFlat) {
-        const double v = b[t] - mean;
+        const int64_t i = t / nphi;
+        const int64_t src = (int64_t)perm[i] * nphi + (t - i * nphi);
+        const double v = b[src] - mean;
         bint[t] = v;
-        if (!warm) x[t] = 0.0;
+        x[t] = warm ? p0[src] : 0.0;
         d0[t] = 0.0;
         d1[t] = 0.0;
         acc[0] = fma(v, v, acc[0]);
@@ -293,14 +429,43 @@ __global__ __launch_bounds__(kBlockFlat) void k_finish_reduce(const double* __re
     }
 }
 
-__global__ __launch_bounds__(kBlockFlat) void k_gauge_out(int64_t n, const double* __restrict__ x,
+// p (caller order) = x (internal order) - int x / |Omega|, scattered through perm
+__global__ __launch_bounds__(kBlockFlat) void k_gauge_out(int64_t n, int nphi,
+                                                          const int* __restrict__ perm,
+                                                          const double* __restrict__ x,
                                                           const double* __restrict__ scal,
                                                           double inv_area, double* __restrict__ out) {
     const double shift = scal[S::INTX] * inv_area;
     const bool zero = scal[S::ZERO] != 0.0;
     for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * kBlockFlat)
-        out[t] = zero ? 0.0 : x[t] - shift;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        const int64_t i = t / nphi;
+        out[(int64_t)perm[i] * nphi + (t - i * nphi)] = zero ? 0.0 : x[t] - shift;
+    }
+}
+
+// K p in internal order (the standalone operator kernel on the internal tables)
+template <int P>
+__global__ __launch_bounds__(kBlockTri) void k_apply_internal(const RefOps<P>* __restrict__ ops,
+                                                              const double4* __restrict__ geo,
+                                                              const int4* __restrict__ nbr,
+                                                              int64_t ne,
+                                                              const double* __restrict__ p,
+                                                              double* __restrict__ out) {
+    constexpr int N = RefOps<P>::NPHI;
+    __shared__ double sm[kTriPerBlock][4][N];
+    const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
+    const int64_t i = (int64_t)blockIdx.x * kTriPerBlock + tl;
+    const bool valid = i < ne;
+    if (valid) {
+        double pl[N], y[N];
+        LoadPlain<N> ld{p};
+        schur_edge_lane<P>(i, al, *ops, geo, nbr, ld, pl, y);
+        lds_scatter<P>(&sm[tl][0][0], al, y);
+    }
+    __syncthreads();
+    if (valid)
+        for (int k = al; k < N; k += 3) out[i * N + k] = sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k];
 }
 
 template <int P>
@@ -317,11 +482,6 @@ const RefOps<P>* ops_of(const sld_disc_s* d) { return reinterpret_cast<const Ref
 
 }  // namespace
 
-int cg_grid(int64_t ne) {
-    const int64_t tiles = (ne + kTriPerBlock - 1) / kTriPerBlock;
-    return (int)(tiles < kCgMaxGrid ? tiles : kCgMaxGrid);
-}
-
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
                            double rtol, int maxit, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
@@ -331,18 +491,14 @@ hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p
     hipLaunchKernelGGL(k_sum_partials, dim3(G), dim3(kBlockFlat), 0, s, b, n, w.part_s);
     hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal,
                        (int)S::MEAN, 1.0 / (double)n);
-    if (warm) {
-        hipError_t e = hipMemcpyAsync(w.x, p0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_cg_prep, dim3(G), dim3(kBlockFlat), 0, s, b, n, w.b, w.x, warm ? 1 : 0,
-                       w.d[0], w.q[0], w.part_s, w.scal);
+    hipLaunchKernelGGL(k_cg_prep, dim3(G), dim3(kBlockFlat), 0, s, b, p0, m->perm, d->nphi, n, w.b,
+                       w.x, warm ? 1 : 0, w.d[0], w.q[0], w.part_s, w.scal);
     hipLaunchKernelGGL(k_cg_scal_init, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal, rtol,
                        maxit);
     // r_0 = K x - b_int (the residual of -K x = -b_int); q, d of "iteration -1" are zero
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(G), dim3(kBlockTri), 0, s,
-                                          ops_of<PP>(d), m->geo, m->nbr, m->ne, w.x, w.b, w.r[0],
-                                          w.part_s, w.scal));
+                                          ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
+                                          w.r[0], w.part_s, w.scal));
     return hipGetLastError();
 }
 
@@ -351,27 +507,47 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
     const CgWork& w = d->cg;
     const int G = w.grid;
     const int o = 1 - parity;
+    if (w.wave_kernel) {
+        const size_t lds = wave_lds_bytes(d->nphi, m->hmax);
+        SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_step_wave<PP>, dim3(G), dim3(kBlockWave), lds,
+                                              s, ops_of<PP>(d), m->geo_i, m->nbr_i, m->halo_off,
+                                              m->halo_ids, m->hmax, m->ne, w.x, w.r[parity],
+                                              w.q[parity], w.d[parity], w.r[o], w.q[o], w.d[o],
+                                              w.part + parity * 4 * G, w.part + o * 4 * G,
+                                              w.scal, parity));
+        return hipGetLastError();
+    }
     const size_t lds = step_lds_bytes(d->nphi, m->hmax);
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_step<PP>, dim3(G), dim3(kBlockTri), lds, s,
-                                          ops_of<PP>(d), m->geo, m->nbr, m->halo_off, m->halo_ids,
-                                          m->hmax, m->ne, w.x, w.r[parity], w.q[parity],
+                                          ops_of<PP>(d), m->geo_i, m->nbr_i, m->halo_off,
+                                          m->halo_ids, m->hmax, m->ne, w.x, w.r[parity], w.q[parity],
                                           w.d[parity], w.r[o], w.q[o], w.d[o],
                                           w.part + parity * 4 * G, w.part + o * 4 * G, w.scal,
                                           parity));
     return hipGetLastError();
 }
 
+int cg_grid_for(int64_t ne, bool wave_kernel) {
+    const int64_t tiles = (ne + kTriPerBlock - 1) / kTriPerBlock;
+    if (!wave_kernel) return (int)(tiles < kCgMaxGrid ? tiles : kCgMaxGrid);
+    const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    return (int)(blocks < kCgMaxGridWave ? blocks : kCgMaxGridWave);
+}
+
 hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     const CgWork& w = d->cg;
     const int G = w.grid;
-    hipError_t e = launch_schur_apply(d, w.x, w.q[0], 1.0, s);
-    if (e != hipSuccess) return e;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_apply_internal<PP>,
+                                          dim3((unsigned)((m->ne + kTriPerBlock - 1) / kTriPerBlock)),
+                                          dim3(kBlockTri), 0, s, ops_of<PP>(d), m->geo_i, m->nbr_i,
+                                          m->ne, w.x, w.q[0]));
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_finish_partials<PP>, dim3(G), dim3(kBlockFlat), 0, s,
-                                          ops_of<PP>(d), m->geo, m->ne, w.q[0], w.b, w.x, w.part_s));
+                                          ops_of<PP>(d), m->geo_i, m->ne, w.q[0], w.b, w.x,
+                                          w.part_s));
     hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal);
     const int64_t n = m->ne * d->nphi;
-    hipLaunchKernelGGL(k_gauge_out, dim3(G), dim3(kBlockFlat), 0, s, n, w.x, w.scal,
-                       1.0 / m->area_total, p_out);
+    hipLaunchKernelGGL(k_gauge_out, dim3(G), dim3(kBlockFlat), 0, s, n, d->nphi, m->perm, w.x,
+                       w.scal, 1.0 / m->area_total, p_out);
     return hipGetLastError();
 }

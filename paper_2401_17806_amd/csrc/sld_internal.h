@@ -41,18 +41,26 @@ struct sld_mesh_s {
     std::vector<double> shift;     // [nd][2] r's frame minus l's frame
     // device
     double4* geo = nullptr;        // [ne] (e1x, e1y, e2x, e2y): e1 = P1-P0, e2 = P2-P0
-    int4* nbr = nullptr;           // [ne] packed neighbour across local edges 0,1,2; w = the three
+    int4* nbr = nullptr;           // [ne] packed neighbour across local edges 0,1,2; w unused
+    // Internal triangle order of the CG (a Morton curve over centroids, so that tiles of
+    // consecutive triangles are compact patches with small halos):
+    int* perm = nullptr;           // [ne] internal index -> caller's triangle index
+    double4* geo_i = nullptr;      // [ne] geo in internal order
+    int4* nbr_i = nullptr;         // [ne] internal neighbour ids (packed as nbr); w = the three
                                    // tile-local slots (10 bits each): 0..63 own tile, 64+h halo
     int* halo_off = nullptr;       // [ntiles + 1] offsets into halo_ids
-    int* halo_ids = nullptr;       // halo triangles of every tile, sorted per tile
+    int* halo_ids = nullptr;       // halo triangles (internal ids) of every tile, sorted
     int hmax = 0;                  // largest halo
+    int64_t halo_total = 0;        // sum of halo sizes (diagnostics)
     int4* edges = nullptr;         // [nd] (l, r, alpha_l, alpha_r)
     int4* tedges = nullptr;        // [ne] (2*j + beta) per local edge; beta = 1 if i = r(j)
     double area_total = 0;         // |Omega|
 };
 
 // Workspace of the CG solver (allocated with the disc).
-constexpr int kCgMaxGrid = 1024;  // blocks of every CG kernel (grid-stride beyond)
+constexpr int kCgMaxGrid = 4096;     // blocks of the three-lane CG kernel (grid-stride beyond)
+constexpr int kCgMaxGridWave = 768;  // blocks of the wave-per-tile CG kernel
+constexpr int64_t kWaveKernelMinTri = 131072;  // meshes at least this large use the wave kernel
 struct CgWork {
     double* x = nullptr;
     double* r[2] = {nullptr, nullptr};  // ping-pong by iteration parity
@@ -64,6 +72,7 @@ struct CgWork {
     double* scal = nullptr;        // device scalars (CgScalars)
     double* host_scal = nullptr;   // pinned mirror of scal
     int grid = 0;                  // blocks of every CG kernel
+    bool wave_kernel = false;      // iteration kernel variant (by mesh size)
     std::vector<hipEvent_t> events;  // profiling events (created on first profiled solve)
     hipStream_t capture = nullptr;   // private stream used to capture the iteration graph
     hipGraphExec_t graph = nullptr;  // captured block of iterations
@@ -93,7 +102,7 @@ struct CgScalars {
     enum { RR = 0, BB = 1, TOL2 = 2, ITER = 3, DONE = 4, MAXIT = 5, MEAN = 6, ZERO = 7,
            RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, NSCAL = 16 };
 };
-int cg_grid(int64_t ne);
+int cg_grid_for(int64_t ne, bool wave_kernel);
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
                            double rtol, int maxit, hipStream_t s);
 hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s);
