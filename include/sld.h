@@ -82,6 +82,7 @@ sld_status sld_mesh_counts(sld_mesh mesh, int64_t* ne, int64_t* nd, int64_t* nv)
  * any pointer may be NULL. */
 sld_status sld_mesh_edges(sld_mesh mesh, int32_t* left, int32_t* right,
                           int32_t* alpha_left, int32_t* alpha_right);
+/* Drops the caller's handle; the mesh lives on while discs built on it exist. */
 void sld_mesh_destroy(sld_mesh mesh);
 
 /* ------------------------------------------------------------------ discretisation
@@ -89,7 +90,9 @@ void sld_mesh_destroy(sld_mesh mesh);
  * reference divergence/gradient operators, here in the equivalent form of reference
  * stiffness, edge-node derivative and sub-triangle correction matrices), computed on the
  * host in float64 by exact Gauss quadrature, plus the solver workspace on the device.
- * The mesh must outlive the disc.  flags: reserved, pass 0. */
+ * The disc holds a reference to its mesh: sld_mesh_destroy may come before sld_disc_destroy,
+ * and the mesh is freed when its handle and every disc built on it are destroyed.
+ * flags: reserved, pass 0. */
 sld_status sld_disc_create(sld_mesh mesh, int32_t p, uint32_t flags, sld_disc* out);
 sld_status sld_disc_info(sld_disc disc, int32_t* p, int32_t* nphi, int32_t* npsi);
 /* Host float64 [ne][N_phi][2] physical positions of the main DOF nodes (each triangle in
@@ -136,29 +139,66 @@ sld_status sld_velocity_correct(sld_disc disc, const double* v_star, const doubl
  * (fixed-order reductions, no atomics).  On SLD_E_NOCONV p holds
  * the last iterate and the report is filled. */
 typedef struct {
-    double rtol;          /* relative residual tolerance, e.g. 1e-12 */
-    int32_t maxit;        /* iteration cap */
+    double rtol;          /* relative residual tolerance, e.g. 1e-12 (FP64) / 1e-11 (mixed) */
+    double inner_rtol;    /* mixed only: reduction of the FP32 residual between two FP64
+                             reliable updates (refreshes of x and of the true residual), e.g. 0.3 */
+    int32_t maxit;        /* iteration cap (mixed: per inner solve) */
     int32_t warm_start;   /* nonzero: p holds the initial guess */
     int32_t graph_block;  /* iterations per convergence check (even, 2..4096) */
     int32_t profile;      /* nonzero: launch the iterations one by one (no graph) with a HIP
                              event after each on `stream`; the report gives the mean time
-                             between consecutive iteration kernels */
-    int32_t reserved;     /* pass 0 */
+                             between consecutive iteration kernels (FP64 only) */
+    int32_t precision;    /* 0: FP64 CG.  1: mixed: one CG process in FP32 (FP32 vectors and
+                             operator arithmetic; FP64 geometry and dot products) refreshed by
+                             FP64 reliable updates (x accumulated in FP64, residual b - K x
+                             recomputed in FP64, search direction kept).  Stops at rtol on the
+                             FP64 residual, or when it no longer improves (rounding floor) */
+    int32_t max_outer;    /* mixed only: cap on reliable updates */
 } sld_cg_params;
 
 typedef struct {
-    int32_t iters;        /* CG iterations performed */
-    int32_t converged;    /* 1 if the recursive residual met rtol */
-    double rel_res;       /* recursive residual ||r_k|| / ||b|| */
+    int32_t iters;        /* CG iterations performed (mixed: inner iterations, summed) */
+    int32_t converged;    /* 1 if rtol was met */
+    double rel_res;       /* ||r|| / ||b|| at exit (FP64: recursive; mixed: FP64 residual) */
     double rel_res_true;  /* ||b - K p|| / ||b|| recomputed at exit */
     double seconds;       /* wall time of the solve on the host */
     double step_us;       /* profile only: mean duration of one CG iteration kernel */
     int32_t timed_iters;  /* profile only: iterations the mean is taken over */
-    int32_t reserved;
+    int32_t outer_iters;  /* mixed only: reliable updates performed */
 } sld_cg_report;
 
 sld_status sld_cg_solve(sld_disc disc, const double* b, double* p, const sld_cg_params* params,
                         sld_cg_report* report, void* stream);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of independent pressure solves (the paper's pressure stage of
+ * eq. pressure_final, one per request).  Requests are queued as they arrive; a worker thread
+ * admits the first queued request whose disc is idle and whose footprint fits the remaining
+ * memory budget (one request is always admitted when none runs), and runs sld_cg_solve on its
+ * own HIP stream, so requests overlap on the device.  Requests on the same disc run in turn
+ * (the disc owns the CG workspace).  Results are bitwise independent of the mix.
+ *
+ * sld_disc_footprint: device bytes a solve on `disc` uses (geometry, tables, workspace). */
+typedef struct sld_server_s* sld_server;
+sld_status sld_disc_footprint(sld_disc disc, uint64_t* bytes);
+/* hbm_budget_bytes: cap on the summed footprint (plus b and p) of running requests;
+ * nworkers: concurrent solves (1..64), each with its own default-priority HIP stream. */
+sld_status sld_server_create(int32_t device, uint64_t hbm_budget_bytes, int32_t nworkers,
+                             sld_server* out);
+/* Queue a solve of K p = b on `disc`.  b, p: device [ne][N_phi] buffers that must stay valid
+ * until the ticket completes.  The solve waits for work already queued on `stream` (the
+ * submitter's stream, NULL = default stream) before reading b.  SLD_E_BUDGET if the request
+ * alone exceeds the budget. */
+sld_status sld_server_submit(sld_server server, sld_disc disc, const double* b, double* p,
+                             const sld_cg_params* params, void* stream, uint64_t* ticket);
+/* Completion of a ticket: *done = 1 when p holds the result (then *status is the solve's
+ * sld_status and *report its report, and the ticket is retired).  wait != 0 blocks until done. */
+sld_status sld_server_poll(sld_server server, uint64_t ticket, int32_t wait, int32_t* done,
+                           int32_t* status, sld_cg_report* report);
+sld_status sld_server_stats(sld_server server, int32_t* queued, int32_t* running,
+                            uint64_t* in_flight_bytes, uint64_t* completed);
+/* Finishes every queued request, then joins the workers. */
+void sld_server_destroy(sld_server server);
 
 #ifdef __cplusplus
 }

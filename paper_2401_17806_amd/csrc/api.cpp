@@ -8,6 +8,7 @@
 #include <new>
 #include <string>
 #include <unordered_map>
+#include <mutex>
 #include <vector>
 
 #include "sld_internal.h"
@@ -25,6 +26,35 @@ struct DeviceGuard {
     }
     ~DeviceGuard() {
         if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Graph capture on one thread and device setup or teardown on another must not overlap: the
+// runtime rejects synchronous copies and may serialise frees against a capturing stream.  Every
+// capture, and every create/destroy that touches device memory, holds this lock.
+std::mutex& device_setup_mutex() {
+    static std::mutex mu;
+    return mu;
+}
+
+// Host -> device uploads and clears during setup run on a private non-blocking stream (never
+// the legacy null stream), then wait for it.
+struct Uploader {
+    hipStream_t s = nullptr;
+    hipError_t err = hipSuccess;
+    Uploader() { err = hipStreamCreateWithFlags(&s, hipStreamNonBlocking); }
+    ~Uploader() {
+        if (s) (void)hipStreamDestroy(s);
+    }
+    void copy(void* dst, const void* src, size_t bytes) {
+        if (err == hipSuccess && bytes) err = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    }
+    void zero(void* dst, size_t bytes) {
+        if (err == hipSuccess && bytes) err = hipMemsetAsync(dst, 0, bytes, s);
+    }
+    hipError_t finish() {
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        return err;
     }
 };
 
@@ -52,6 +82,18 @@ void free_mesh(sld_mesh_s* m) {
     delete m;
 }
 
+// Drop one reference; the last one frees host tables and device memory.
+void release_mesh(sld_mesh_s* m) {
+    if (m->refs.fetch_sub(1) != 1) return;
+    if (m->device < 0) {
+        free_mesh(m);
+        return;
+    }
+    DeviceGuard dg(m->device);
+    std::lock_guard<std::mutex> lk(device_setup_mutex());
+    free_mesh(m);
+}
+
 template <int P>
 size_t ops_size() { return sizeof(RefOps<P>); }
 
@@ -75,6 +117,27 @@ int build_ops(int p, void** host, size_t* bytes) {
             return -2;
     }
     return rc;
+}
+
+// float copy of the operators (built on the host, uploaded once)
+size_t ops32_bytes(int p) {
+    switch (p) {
+        case 1: return sizeof(RefOps32<1>);
+        case 2: return sizeof(RefOps32<2>);
+        case 3: return sizeof(RefOps32<3>);
+        case 4: return sizeof(RefOps32<4>);
+        default: return 0;
+    }
+}
+
+void round_ops(int p, const void* in, void* out) {
+    switch (p) {
+        case 1: round_refops<1>(*static_cast<const RefOps<1>*>(in), static_cast<RefOps32<1>*>(out)); break;
+        case 2: round_refops<2>(*static_cast<const RefOps<2>*>(in), static_cast<RefOps32<2>*>(out)); break;
+        case 3: round_refops<3>(*static_cast<const RefOps<3>*>(in), static_cast<RefOps32<3>*>(out)); break;
+        case 4: round_refops<4>(*static_cast<const RefOps<4>*>(in), static_cast<RefOps32<4>*>(out)); break;
+        default: break;
+    }
 }
 
 void free_ops_host(int p, void* h) {
@@ -109,6 +172,17 @@ void free_disc(sld_disc_s* d) {
     dfree(w.b);
     dfree(w.part);
     dfree(w.part_s);
+    for (int k = 0; k < 2; ++k) {
+        dfree(w.r32[k]);
+        dfree(w.q32[k]);
+        dfree(w.d32[k]);
+    }
+    dfree(w.e32);
+    dfree(w.part32);
+    dfree(w.scal_in);
+    if (w.host_scal_in) (void)hipHostFree(w.host_scal_in);
+    if (w.graph32) (void)hipGraphExecDestroy(w.graph32);
+    dfree(d->ops32_dev);
     dfree(w.scal);
     if (w.graph) (void)hipGraphExecDestroy(w.graph);
     if (w.capture) (void)hipStreamDestroy(w.capture);
@@ -377,7 +451,9 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
             sld_set_error("sld_mesh_create: hipSetDevice failed");
             return SLD_E_HIP;
         }
-        hipError_t e = hipSuccess;
+        std::lock_guard<std::mutex> lk(device_setup_mutex());
+        Uploader up;
+        hipError_t e = up.err;
         if (e == hipSuccess) e = dalloc(&m->geo, ne);
         if (e == hipSuccess) e = dalloc(&m->nbr, ne);
         if (e == hipSuccess) e = dalloc(&m->tedges, ne);
@@ -385,25 +461,20 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
         if (e == hipSuccess) e = dalloc(&m->perm, ne);
         if (e == hipSuccess) e = dalloc(&m->geo_i, ne);
         if (e == hipSuccess) e = dalloc(&m->nbr_i, ne);
-        if (e == hipSuccess) e = hipMemcpy(m->perm, perm.data(), sizeof(int) * ne, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(m->geo_i, geo_i.data(), sizeof(double4) * ne, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(m->nbr_i, nbr_i.data(), sizeof(int4) * ne, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = dalloc(&m->halo_off, halo_off.size());
         if (e == hipSuccess) e = dalloc(&m->halo_ids, halo_ids.size());
-        if (e == hipSuccess)
-            e = hipMemcpy(m->halo_off, halo_off.data(), sizeof(int) * halo_off.size(),
-                          hipMemcpyHostToDevice);
-        if (e == hipSuccess && !halo_ids.empty())
-            e = hipMemcpy(m->halo_ids, halo_ids.data(), sizeof(int) * halo_ids.size(),
-                          hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(m->geo, geo.data(), sizeof(double4) * ne, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(m->nbr, nbr.data(), sizeof(int4) * ne, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(m->tedges, tedges.data(), sizeof(int4) * ne, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(m->edges, edges.data(), sizeof(int4) * m->nd, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            up.copy(m->perm, perm.data(), sizeof(int) * ne);
+            up.copy(m->geo_i, geo_i.data(), sizeof(double4) * ne);
+            up.copy(m->nbr_i, nbr_i.data(), sizeof(int4) * ne);
+            up.copy(m->halo_off, halo_off.data(), sizeof(int) * halo_off.size());
+            up.copy(m->halo_ids, halo_ids.data(), sizeof(int) * halo_ids.size());
+            up.copy(m->geo, geo.data(), sizeof(double4) * ne);
+            up.copy(m->nbr, nbr.data(), sizeof(int4) * ne);
+            up.copy(m->tedges, tedges.data(), sizeof(int4) * ne);
+            up.copy(m->edges, edges.data(), sizeof(int4) * m->nd);
+            e = up.finish();
+        }
         if (e != hipSuccess) {
             free_mesh(m);
             sld_set_error(std::string("sld_mesh_create: device setup failed: ") + hipGetErrorString(e));
@@ -438,13 +509,7 @@ sld_status sld_mesh_edges(sld_mesh m, int32_t* left, int32_t* right, int32_t* al
 }
 
 void sld_mesh_destroy(sld_mesh m) {
-    if (!m) return;
-    if (m->device < 0) {
-        free_mesh(m);
-        return;
-    }
-    DeviceGuard dg(m->device);
-    free_mesh(m);
+    if (m) release_mesh(m);
 }
 
 sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out) {
@@ -466,6 +531,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         return rc == -1 ? SLD_E_NOMEM : SLD_E_INVALID;
     }
     if (m->device < 0) {
+        m->refs.fetch_add(1);
         *out = d;  // host-only: reference operators and node queries only
         return SLD_OK;
     }
@@ -482,8 +548,13 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         if (cap > 0 && cap < G) G = cap;
     }
     w.grid = G;
-    hipError_t e = hipMalloc(&d->ops_dev, d->ops_bytes);
-    if (e == hipSuccess) e = hipMemcpy(d->ops_dev, d->ops_host, d->ops_bytes, hipMemcpyHostToDevice);
+    std::lock_guard<std::mutex> lk(device_setup_mutex());
+    Uploader up;
+    std::vector<unsigned char> h32(ops32_bytes(p));
+    round_ops(p, d->ops_host, h32.data());
+    hipError_t e = up.err;
+    if (e == hipSuccess) e = hipMalloc(&d->ops_dev, d->ops_bytes);
+    if (e == hipSuccess) e = hipMalloc(&d->ops32_dev, h32.size());
     if (e == hipSuccess) e = dalloc(&w.x, nv);
     for (int k = 0; k < 2; ++k) {
         if (e == hipSuccess) e = dalloc(&w.r[k], nv);
@@ -494,7 +565,24 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     if (e == hipSuccess) e = dalloc(&w.part, size_t(8) * G);
     if (e == hipSuccess) e = dalloc(&w.part_s, size_t(2) * G);
     if (e == hipSuccess) e = dalloc(&w.scal, CgScalars::NSCAL);
-    if (e == hipSuccess) e = hipMemset(w.scal, 0, CgScalars::NSCAL * sizeof(double));
+    for (int k = 0; k < 2; ++k) {
+        if (e == hipSuccess) e = dalloc(&w.r32[k], nv);
+        if (e == hipSuccess) e = dalloc(&w.q32[k], nv);
+        if (e == hipSuccess) e = dalloc(&w.d32[k], nv);
+    }
+    if (e == hipSuccess) e = dalloc(&w.e32, nv);
+    if (e == hipSuccess) e = dalloc(&w.part32, size_t(8) * G);
+    if (e == hipSuccess) e = dalloc(&w.scal_in, CgScalars::NSCAL);
+    if (e == hipSuccess) {
+        up.copy(d->ops_dev, d->ops_host, d->ops_bytes);
+        up.copy(d->ops32_dev, h32.data(), h32.size());
+        up.zero(w.scal, CgScalars::NSCAL * sizeof(double));
+        up.zero(w.scal_in, CgScalars::NSCAL * sizeof(double));
+        e = up.finish();
+    }
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&w.host_scal_in), CgScalars::NSCAL * sizeof(double),
+                          hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), CgScalars::NSCAL * sizeof(double),
@@ -504,6 +592,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         sld_set_error(std::string("sld_disc_create: device allocation failed: ") + hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? SLD_E_NOMEM : SLD_E_HIP;
     }
+    m->refs.fetch_add(1);
     *out = d;
     return SLD_OK;
 }
@@ -582,12 +671,15 @@ sld_status sld_main_weights(sld_disc d, double* w_out) {
 
 void sld_disc_destroy(sld_disc d) {
     if (!d) return;
-    if (d->mesh->device < 0) {
+    sld_mesh_s* m = d->mesh;
+    if (m->device < 0) {
         free_disc(d);
-        return;
+    } else {
+        DeviceGuard dg(m->device);
+        std::lock_guard<std::mutex> lk(device_setup_mutex());
+        free_disc(d);
     }
-    DeviceGuard dg(d->mesh->device);
-    free_disc(d);
+    release_mesh(m);
 }
 
 #define SLD_REQUIRE_DEVICE(d, fn) \
@@ -637,6 +729,107 @@ sld_status sld_velocity_correct(sld_disc d, const double* v_star, const double* 
     return SLD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Capture one block of gb CG iterations (FP64 or the FP32 inner solve) into a graph.
+hipError_t capture_block(sld_disc_s* d, bool fp32, int gb, hipGraphExec_t* out) {
+    CgWork& w = d->cg;
+    if (*out) {
+        hipError_t e = hipGraphExecDestroy(*out);
+        *out = nullptr;
+        if (e != hipSuccess) return e;
+    }
+    hipGraph_t g = nullptr;
+    std::lock_guard<std::mutex> lk(device_setup_mutex());
+    hipError_t e = hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t ce = hipSuccess;
+    for (int k = 0; k < gb && ce == hipSuccess; ++k)
+        ce = fp32 ? launch_cg_step32(d, k & 1, w.capture) : launch_cg_step(d, k & 1, w.capture);
+    e = hipStreamEndCapture(w.capture, &g);
+    if (ce != hipSuccess) return ce;
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+struct IterStats {
+    int iters = 0, done = 0, timed = 0;
+    double t_step = 0;
+};
+
+// Run CG iterations until the device flags DONE in `scal` (host mirror `hs`).
+sld_status run_iterations(sld_disc_s* d, bool fp32, int gb, bool prof, hipStream_t s, double* scal,
+                          double* hs, IterStats* st) {
+    typedef CgScalars S;
+    CgWork& w = d->cg;
+    hipGraphExec_t& graph = fp32 ? w.graph32 : w.graph;
+    int& graph_block = fp32 ? w.graph32_block : w.graph_block;
+    if (prof && (int)w.events.size() < gb + 1) {
+        for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
+        w.events.assign(gb + 1, nullptr);
+        for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
+    }
+    if (!prof && (graph == nullptr || graph_block != gb)) {
+        SLD_HIP_CHECK(capture_block(d, fp32, gb, &graph));
+        graph_block = gb;
+    }
+    int launched = 0;
+    while (true) {
+        if (prof) {
+            SLD_HIP_CHECK(hipEventRecord(w.events[0], s));
+            for (int k = 0; k < gb; ++k) {
+                SLD_HIP_CHECK(fp32 ? launch_cg_step32(d, k & 1, s) : launch_cg_step(d, k & 1, s));
+                SLD_HIP_CHECK(hipEventRecord(w.events[k + 1], s));
+            }
+        } else {
+            SLD_HIP_CHECK(hipGraphLaunch(graph, s));
+        }
+        SLD_HIP_CHECK(hipMemcpyAsync(hs, scal, S::NSCAL * sizeof(double), hipMemcpyDeviceToHost, s));
+        SLD_HIP_CHECK(hipStreamSynchronize(s));
+        st->done = (int)hs[S::DONE];
+        const int before = launched;
+        // launches that did work: the counter of the slot written last
+        launched = (int)std::max(hs[S::ITER0], hs[S::ITER1]);
+        st->iters = st->done ? (int)hs[S::ITER] : launched - 1;
+        if (prof) {
+            const int nk = launched - before;
+            for (int k = 0; k < nk && k < gb; ++k) {
+                float a = 0;
+                SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[k], w.events[k + 1]));
+                st->t_step += a;
+                ++st->timed;
+            }
+        }
+        if (st->done) return SLD_OK;
+    }
+}
+
+// One graph block of FP32 inner iterations; st->iters = launches that did work so far - 1.
+sld_status run_block(sld_disc_s* d, int gb, hipStream_t s, IterStats* st) {
+    typedef CgScalars S;
+    CgWork& w = d->cg;
+    if (w.graph32 == nullptr || w.graph32_block != gb) {
+        SLD_HIP_CHECK(capture_block(d, true, gb, &w.graph32));
+        w.graph32_block = gb;
+    }
+    SLD_HIP_CHECK(hipGraphLaunch(w.graph32, s));
+    SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal_in, w.scal_in, S::NSCAL * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+    SLD_HIP_CHECK(hipStreamSynchronize(s));
+    const int launched = (int)std::max(w.host_scal_in[S::ITER0], w.host_scal_in[S::ITER1]);
+    st->done = (int)w.host_scal_in[S::DONE];
+    st->iters = st->done ? (int)w.host_scal_in[S::ITER] : launched - 1;
+    return SLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_params* prm,
                         sld_cg_report* rep, void* stream) {
     SLD_REQUIRE(d && b && p && prm, SLD_E_INVALID, "sld_cg_solve: NULL argument");
@@ -645,93 +838,130 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
     SLD_REQUIRE(prm->maxit >= 1, SLD_E_INVALID, "sld_cg_solve: maxit must be >= 1");
     SLD_REQUIRE(prm->graph_block >= 2 && prm->graph_block % 2 == 0 && prm->graph_block <= 4096,
                 SLD_E_INVALID, "sld_cg_solve: graph_block must be even and in [2, 4096]");
+    SLD_REQUIRE(prm->precision == 0 || prm->precision == 1, SLD_E_INVALID,
+                "sld_cg_solve: precision must be 0 (FP64) or 1 (mixed)");
+    const bool mixed = prm->precision == 1;
+    if (mixed) {
+        SLD_REQUIRE(prm->inner_rtol > 0 && prm->inner_rtol < 1, SLD_E_INVALID,
+                    "sld_cg_solve: inner_rtol must be in (0, 1)");
+        SLD_REQUIRE(prm->max_outer >= 1, SLD_E_INVALID, "sld_cg_solve: max_outer must be >= 1");
+        SLD_REQUIRE(prm->profile == 0, SLD_E_INVALID, "sld_cg_solve: profile is FP64-only");
+    }
     SLD_REQUIRE_DEVICE(d, "sld_cg_solve");
     DeviceGuard dg(d->mesh->device);
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
     CgWork& w = d->cg;
-    SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, s));
     typedef CgScalars S;
-    const bool prof = prm->profile != 0;
-    const int gb = prm->graph_block;
-    if (prof && (int)w.events.size() < gb + 1) {
-        for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
-        w.events.assign(gb + 1, nullptr);
-        for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
-    }
-    if (!prof && (w.graph == nullptr || w.graph_block != gb)) {
-        // capture one block of gb iterations on the private stream
-        if (w.graph) {
-            SLD_HIP_CHECK(hipGraphExecDestroy(w.graph));
-            w.graph = nullptr;
-        }
-        hipGraph_t g = nullptr;
-        SLD_HIP_CHECK(hipStreamBeginCapture(w.capture, hipStreamCaptureModeThreadLocal));
-        hipError_t ce = hipSuccess;
-        for (int k = 0; k < gb && ce == hipSuccess; ++k) ce = launch_cg_step(d, k & 1, w.capture);
-        hipError_t ee = hipStreamEndCapture(w.capture, &g);
-        SLD_HIP_CHECK(ce);
-        SLD_HIP_CHECK(ee);
-        hipError_t ie = hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        SLD_HIP_CHECK(ie);
-        w.graph_block = gb;
-    }
-    int iters = 0, done = 0, timed = 0;
-    double t_step = 0;
-    int launched = 0;
-    while (true) {
-        if (prof) {
-            // iterations launched one by one with an event after each (kernel timing)
-            SLD_HIP_CHECK(hipEventRecord(w.events[0], s));
-            for (int k = 0; k < gb; ++k) {
-                SLD_HIP_CHECK(launch_cg_step(d, k & 1, s));
-                SLD_HIP_CHECK(hipEventRecord(w.events[k + 1], s));
+    SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, s));
+    IterStats st;
+    int outer = 0, status = 0;  // status: 1 converged, 2 no convergence, 3 breakdown
+    double rr = 0, bb = 0;
+    if (!mixed) {
+        sld_status e = run_iterations(d, false, prm->graph_block, prm->profile != 0, s, w.scal,
+                                      w.host_scal, &st);
+        if (e != SLD_OK) return e;
+        rr = w.host_scal[S::RR];
+        bb = w.host_scal[S::BB];
+        status = st.done;
+    } else {
+        // FP32 CG with FP64 reliable updates.  The setup left r64 = K x - b_int (partials in
+        // part_s); one Krylov process runs in FP32 and is refreshed in FP64 whenever its
+        // residual has dropped by `refresh` since the last refresh, and when it believes it
+        // has converged (the FP64 residual then decides).
+        const double refresh = prm->inner_rtol;
+        int total = 0, base = 0;
+        SLD_HIP_CHECK(launch_rel_init(d, prm->rtol, prm->maxit, s));
+        double rr_ref = 1.0;   // scaled rr at the last refresh
+        double prev64 = -1.0;  // FP64 rr at the previous restart
+        double last64 = -1.0;  // FP64 rr at the previous refresh
+        while (true) {
+            // graph blocks of FP32 iterations until the residual has dropped by `refresh`
+            // since the last refresh, or the FP32 process stops on its own criterion
+            IterStats in;
+            while (true) {
+                sld_status e = run_block(d, prm->graph_block, s, &in);
+                if (e != SLD_OK) return e;
+                if (in.done) break;
+                SLD_HIP_CHECK(launch_rel_peek(d, 0, s));
+                SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal_in, w.scal_in, S::NSCAL * sizeof(double),
+                                             hipMemcpyDeviceToHost, s));
+                SLD_HIP_CHECK(hipStreamSynchronize(s));
+                if (w.host_scal_in[S::RRNOW] <= refresh * refresh * rr_ref) break;
             }
-        } else {
-            SLD_HIP_CHECK(hipGraphLaunch(w.graph, s));
-        }
-        SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
-                                     hipMemcpyDeviceToHost, s));
-        SLD_HIP_CHECK(hipStreamSynchronize(s));
-        done = (int)w.host_scal[S::DONE];
-        const int before = launched;
-        // launches that did work: the counter of the slot written last
-        launched = (int)std::max(w.host_scal[S::ITER0], w.host_scal[S::ITER1]);
-        iters = done ? (int)w.host_scal[S::ITER] : launched - 1;
-        if (prof) {
-            const int nk = launched - before;
-            for (int k = 0; k < nk && k < gb; ++k) {
-                float a = 0;
-                SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[k], w.events[k + 1]));
-                t_step += a;
-                ++timed;
+            total = base + in.iters;
+            // reliable update in float64 (a restart of the FP32 process if it had stopped)
+            const int restart = in.done != 0;
+            if (restart) base = total;
+            SLD_HIP_CHECK(launch_rel_update(d, restart, s));
+            SLD_HIP_CHECK(launch_rel_peek(d, 0, s));
+            SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
+                                         hipMemcpyDeviceToHost, s));
+            SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal_in, w.scal_in, S::NSCAL * sizeof(double),
+                                         hipMemcpyDeviceToHost, s));
+            SLD_HIP_CHECK(hipStreamSynchronize(s));
+            ++outer;
+            rr = w.host_scal[S::RR];
+            bb = w.host_scal[S::BB];
+            rr_ref = w.host_scal_in[S::RRNOW];
+            if (rr <= w.host_scal[S::TOL2]) {
+                status = 1;
+                break;
             }
+            if (!std::isfinite(rr)) {
+                status = 3;
+                break;
+            }
+            if (in.done == 2 || outer >= prm->max_outer) {
+                status = 2;
+                break;
+            }
+            if (restart) {
+                // the FP32 process met rtol but the FP64 residual did not: go on from the
+                // refreshed residual unless the FP64 residual has stopped improving (floor)
+                if (prev64 >= 0 && rr > 0.25 * prev64) {
+                    status = 2;
+                    break;
+                }
+                prev64 = rr;
+            } else if (last64 >= 0 && rr > last64) {
+                // the FP64 residual grew since the previous refresh: the FP32 directions have
+                // lost conjugacy; restart the FP32 process from the current solution
+                base = total;
+                SLD_HIP_CHECK(launch_rel_update(d, 1, s));
+                SLD_HIP_CHECK(launch_rel_peek(d, 0, s));
+                SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal_in, w.scal_in, S::NSCAL * sizeof(double),
+                                             hipMemcpyDeviceToHost, s));
+                SLD_HIP_CHECK(hipStreamSynchronize(s));
+                rr_ref = w.host_scal_in[S::RRNOW];
+            }
+            last64 = rr;
         }
-        if (done) break;
+        st.iters = total;
     }
-    const double rr = w.host_scal[S::RR], bb = w.host_scal[S::BB];
     SLD_HIP_CHECK(launch_cg_finish(d, p, s));
     SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     SLD_HIP_CHECK(hipStreamSynchronize(s));
     const double rt = w.host_scal[S::RTRUE];
     if (rep) {
-        rep->iters = iters;
-        rep->converged = done == 1;
+        rep->iters = st.iters;
+        rep->converged = status == 1;
         rep->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
         rep->rel_res_true = bb > 0 ? std::sqrt(rt / bb) : 0.0;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        rep->step_us = timed ? 1e3 * t_step / timed : 0.0;
-        rep->timed_iters = timed;
-        rep->reserved = 0;
+        rep->step_us = st.timed ? 1e3 * st.t_step / st.timed : 0.0;
+        rep->timed_iters = st.timed;
+        rep->outer_iters = outer;
     }
-    if (done == 3) {
+    if (status == 3) {
         sld_set_error("sld_cg_solve: breakdown (d.Ad <= 0 or non-finite)");
         return SLD_E_BREAKDOWN;
     }
-    if (done == 2) {
-        sld_set_error("sld_cg_solve: maxit reached before rtol");
+    if (status == 2) {
+        sld_set_error(mixed ? "sld_cg_solve: refinement stopped before rtol (maxit, max_outer or "
+                              "the FP64 residual floor)"
+                            : "sld_cg_solve: maxit reached before rtol");
         return SLD_E_NOCONV;
     }
     return SLD_OK;

@@ -100,6 +100,18 @@ __device__ __forceinline__ void relabel(double4 e, int ar, double& e1x, double& 
     e2y = ar == 0 ? e.w : (ar == 1 ? -e.y : -a1y);
 }
 
+// fused multiply-add in the arithmetic type of the operands
+__device__ __forceinline__ double mad(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float mad(float a, float b, float c) { return fmaf(a, b, c); }
+
+// geometric factors rounded to the arithmetic type
+template <typename Real>
+struct GeoR {
+    Real A, G00, G01, G10, G11;
+    __device__ __forceinline__ explicit GeoR(const Geo& g)
+        : A((Real)g.A), G00((Real)g.G00), G01((Real)g.G01), G10((Real)g.G10), G11((Real)g.G11) {}
+};
+
 __device__ __forceinline__ int pick(int4 v, int al) { return al == 0 ? v.x : (al == 1 ? v.y : v.z); }
 
 // Loaders of a main-grid vector value (t = triangle, l = DOF)
@@ -125,58 +137,59 @@ struct LoadDir {
 // ar (its shared edge is its local edge 0); e / er are the two triangles' edge vectors; nb < 0
 // marks a wall edge.  y receives local rows: this lane's volume rows (orbit representatives)
 // plus the full edge-al term.
-template <int P>
-__device__ __forceinline__ void edge_lane_core(int al, const RefOps<P>& R, double4 e, int nb,
-                                               int ar, double4 er,
-                                               const double (&pl)[RefOps<P>::NPHI],
-                                               const double (&pr)[RefOps<P>::NPHI],
-                                               double (&y)[RefOps<P>::NPHI]) {
+template <int P, class Ops, typename Real>
+__device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, int nb, int ar,
+                                               double4 er, const Real (&pl)[RefOps<P>::NPHI],
+                                               const Real (&pr)[RefOps<P>::NPHI],
+                                               Real (&y)[RefOps<P>::NPHI]) {
     constexpr int N = RefOps<P>::NPHI;
     constexpr int NE = P + 1;
     constexpr Tab<P> T{};
     double e1x, e1y, e2x, e2y;
     relabel(e, al, e1x, e1y, e2x, e2y);
-    const Geo g = make_geo(e1x, e1y, e2x, e2y);
-    const double m00 = g.G00 * g.G00 + g.G01 * g.G01;
-    const double m01 = g.G00 * g.G10 + g.G01 * g.G11;
-    const double m11 = g.G10 * g.G10 + g.G11 * g.G11;
+    // geometric factors in float64, then rounded to the arithmetic type
+    const Geo gd = make_geo(e1x, e1y, e2x, e2y);
+    const GeoR<Real> g(gd);
+    const Real m00 = (Real)(gd.G00 * gd.G00 + gd.G01 * gd.G01);
+    const Real m01 = (Real)(gd.G00 * gd.G10 + gd.G01 * gd.G11);
+    const Real m11 = (Real)(gd.G10 * gd.G10 + gd.G11 * gd.G11);
 #pragma unroll
-    for (int k = 0; k < N; ++k) y[k] = 0.0;
+    for (int k = 0; k < N; ++k) y[k] = Real(0);
     // volume term -A (m00 S0 + m01 S1 + m11 S2) p on this lane's rows
 #pragma unroll
     for (int q = 0; q < T.nrep; ++q) {
         const int k = T.rep[q];
-        double s0 = 0, s1 = 0, s2 = 0;
+        Real s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
         for (int l = 0; l < N; ++l) {
-            s0 = fma(R.S[0][k][l], pl[l], s0);
-            s1 = fma(R.S[1][k][l], pl[l], s1);
-            s2 = fma(R.S[2][k][l], pl[l], s2);
+            s0 = mad(R.S[0][k][l], pl[l], s0);
+            s1 = mad(R.S[1][k][l], pl[l], s1);
+            s2 = mad(R.S[2][k][l], pl[l], s2);
         }
         y[k] = -g.A * (m00 * s0 + m01 * s1 + m11 * s2);
     }
     if (T.centre >= 0 && al == 0) {
         const int k = T.centre >= 0 ? T.centre : 0;
-        double s0 = 0, s1 = 0, s2 = 0;
+        Real s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
         for (int l = 0; l < N; ++l) {
-            s0 = fma(R.S[0][k][l], pl[l], s0);
-            s1 = fma(R.S[1][k][l], pl[l], s1);
-            s2 = fma(R.S[2][k][l], pl[l], s2);
+            s0 = mad(R.S[0][k][l], pl[l], s0);
+            s1 = mad(R.S[1][k][l], pl[l], s1);
+            s2 = mad(R.S[2][k][l], pl[l], s2);
         }
         y[k] = -g.A * (m00 * s0 + m01 * s1 + m11 * s2);
     }
-    const double snx = e1y, sny = -e1x;  // |Gamma| n, outward, of local edge 0
+    const Real snx = (Real)e1y, sny = (Real)(-e1x);  // |Gamma| n, outward, of local edge 0
     if (nb < 0) {
         // wall edge: no dual coupling; give back this sub-triangle's share of the volume term
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            double s0 = 0, s1 = 0, s2 = 0;
+            Real s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
             for (int l = 0; l < N; ++l) {
-                s0 = fma(R.Sh[0][0][k][l], pl[l], s0);
-                s1 = fma(R.Sh[0][1][k][l], pl[l], s1);
-                s2 = fma(R.Sh[0][2][k][l], pl[l], s2);
+                s0 = mad(R.Sh[0][0][k][l], pl[l], s0);
+                s1 = mad(R.Sh[0][1][k][l], pl[l], s1);
+                s2 = mad(R.Sh[0][2][k][l], pl[l], s2);
             }
             y[k] += g.A * (m00 * s0 + m01 * s1 + m11 * s2);
         }
@@ -184,52 +197,53 @@ __device__ __forceinline__ void edge_lane_core(int al, const RefOps<P>& R, doubl
     }
     double f1x, f1y, f2x, f2y;
     relabel(er, ar, f1x, f1y, f2x, f2y);
-    const Geo gr = make_geo(f1x, f1y, f2x, f2y);
-    const double wsum = 1.0 / (g.A + gr.A);
-    double delta[NE];
+    const Geo grd = make_geo(f1x, f1y, f2x, f2y);
+    const GeoR<Real> gr(grd);
+    const Real wsum = (Real)(1.0 / (gd.A + grd.A));
+    Real delta[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) delta[m] = pr[P - m] - pl[m];  // edge-0 nodes are 0..P
-    double gd0[NE], gd1[NE], tn[NE];
+    Real gd0[NE], gd1[NE], tn[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-        double ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
+        Real ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
 #pragma unroll
         for (int l = 0; l < N; ++l) {
-            ds0 = fma(R.E[0][0][m][l], pl[l], ds0);
-            ds1 = fma(R.E[0][1][m][l], pl[l], ds1);
-            dn0 = fma(R.E[0][0][P - m][l], pr[l], dn0);
-            dn1 = fma(R.E[0][1][P - m][l], pr[l], dn1);
+            ds0 = mad(R.E[0][0][m][l], pl[l], ds0);
+            ds1 = mad(R.E[0][1][m][l], pl[l], ds1);
+            dn0 = mad(R.E[0][0][P - m][l], pr[l], dn0);
+            dn1 = mad(R.E[0][1][P - m][l], pr[l], dn1);
         }
-        const double gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
-        const double gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
-        double cd = 0;
+        const Real gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
+        const Real gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
+        Real cd = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) cd = fma(R.C[m][q], delta[q], cd);
-        const double hx = (g.A * gsx + gr.A * gnx + 3.0 * snx * cd) * wsum;
-        const double hy = (g.A * gsy + gr.A * gny + 3.0 * sny * cd) * wsum;
+        for (int q = 0; q < NE; ++q) cd = mad(R.C[m][q], delta[q], cd);
+        const Real hx = (g.A * gsx + gr.A * gnx + Real(3) * snx * cd) * wsum;
+        const Real hy = (g.A * gsy + gr.A * gny + Real(3) * sny * cd) * wsum;
         tn[m] = snx * hx + sny * hy;
-        const double dx = hx - gsx, dy = hy - gsy;
+        const Real dx = hx - gsx, dy = hy - gsy;
         gd0[m] = g.G00 * dx + g.G01 * dy;
         gd1[m] = g.G10 * dx + g.G11 * dy;
     }
     // line term |Gamma| int phi_k n.x_H on the edge nodes
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-        double s = 0;
+        Real s = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) s = fma(R.M1[m][q], tn[q], s);
+        for (int q = 0; q < NE; ++q) s = mad(R.M1[m][q], tn[q], s);
         y[m] += s;
     }
     // sub-triangle correction -A sum_d Pt_d (G Delta)_d
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        double s = 0;
+        Real s = 0;
 #pragma unroll
         for (int m = 0; m < NE; ++m) {
-            s = fma(R.Pt[0][0][k][m], gd0[m], s);
-            s = fma(R.Pt[0][1][k][m], gd1[m], s);
+            s = mad(R.Pt[0][0][k][m], gd0[m], s);
+            s = mad(R.Pt[0][1][k][m], gd1[m], s);
         }
-        y[k] = fma(-g.A, s, y[k]);
+        y[k] = mad(-g.A, s, y[k]);
     }
 }
 
@@ -245,18 +259,19 @@ __device__ __forceinline__ void edge_term(const RefOps<P>& R, const Geo& g, doub
                                           double (&y)[RefOps<P>::NPHI]) {
     constexpr int N = RefOps<P>::NPHI;
     constexpr int NE = P + 1;
+    typedef double Real;
     const double ex = AL == 0 ? e.x : (AL == 1 ? e.z - e.x : -e.z);
     const double ey = AL == 0 ? e.y : (AL == 1 ? e.w - e.y : -e.w);
     const double snx = ey, sny = -ex;  // |Gamma| n, outward
     if (nb < 0) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            double s0 = 0, s1 = 0, s2 = 0;
+            Real s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
             for (int l = 0; l < N; ++l) {
-                s0 = fma(R.Sh[AL][0][k][l], pl[l], s0);
-                s1 = fma(R.Sh[AL][1][k][l], pl[l], s1);
-                s2 = fma(R.Sh[AL][2][k][l], pl[l], s2);
+                s0 = mad(R.Sh[AL][0][k][l], pl[l], s0);
+                s1 = mad(R.Sh[AL][1][k][l], pl[l], s1);
+                s2 = mad(R.Sh[AL][2][k][l], pl[l], s2);
             }
             y[k] += g.A * (m00 * s0 + m01 * s1 + m11 * s2);
         }
@@ -264,50 +279,51 @@ __device__ __forceinline__ void edge_term(const RefOps<P>& R, const Geo& g, doub
     }
     double f1x, f1y, f2x, f2y;
     relabel(er, ar, f1x, f1y, f2x, f2y);
-    const Geo gr = make_geo(f1x, f1y, f2x, f2y);
-    const double wsum = 1.0 / (g.A + gr.A);
-    double delta[NE];
+    const Geo grd = make_geo(f1x, f1y, f2x, f2y);
+    const GeoR<Real> gr(grd);
+    const Real wsum = (Real)(1.0 / (g.A + grd.A));
+    Real delta[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) delta[m] = pr[P - m] - pl[edge_node(P, AL, m)];
-    double gd0[NE], gd1[NE], tn[NE];
+    Real gd0[NE], gd1[NE], tn[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-        double ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
+        Real ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
 #pragma unroll
         for (int l = 0; l < N; ++l) {
-            ds0 = fma(R.E[AL][0][m][l], pl[l], ds0);
-            ds1 = fma(R.E[AL][1][m][l], pl[l], ds1);
-            dn0 = fma(R.E[0][0][P - m][l], pr[l], dn0);
-            dn1 = fma(R.E[0][1][P - m][l], pr[l], dn1);
+            ds0 = mad(R.E[AL][0][m][l], pl[l], ds0);
+            ds1 = mad(R.E[AL][1][m][l], pl[l], ds1);
+            dn0 = mad(R.E[0][0][P - m][l], pr[l], dn0);
+            dn1 = mad(R.E[0][1][P - m][l], pr[l], dn1);
         }
-        const double gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
-        const double gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
-        double cd = 0;
+        const Real gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
+        const Real gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
+        Real cd = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) cd = fma(R.C[m][q], delta[q], cd);
-        const double hx = (g.A * gsx + gr.A * gnx + 3.0 * snx * cd) * wsum;
-        const double hy = (g.A * gsy + gr.A * gny + 3.0 * sny * cd) * wsum;
+        for (int q = 0; q < NE; ++q) cd = mad(R.C[m][q], delta[q], cd);
+        const Real hx = (g.A * gsx + gr.A * gnx + Real(3) * snx * cd) * wsum;
+        const Real hy = (g.A * gsy + gr.A * gny + Real(3) * sny * cd) * wsum;
         tn[m] = snx * hx + sny * hy;
-        const double dx = hx - gsx, dy = hy - gsy;
+        const Real dx = hx - gsx, dy = hy - gsy;
         gd0[m] = g.G00 * dx + g.G01 * dy;
         gd1[m] = g.G10 * dx + g.G11 * dy;
     }
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-        double s = 0;
+        Real s = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) s = fma(R.M1[m][q], tn[q], s);
+        for (int q = 0; q < NE; ++q) s = mad(R.M1[m][q], tn[q], s);
         y[edge_node(P, AL, m)] += s;
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        double s = 0;
+        Real s = 0;
 #pragma unroll
         for (int m = 0; m < NE; ++m) {
-            s = fma(R.Pt[AL][0][k][m], gd0[m], s);
-            s = fma(R.Pt[AL][1][k][m], gd1[m], s);
+            s = mad(R.Pt[AL][0][k][m], gd0[m], s);
+            s = mad(R.Pt[AL][1][k][m], gd1[m], s);
         }
-        y[k] = fma(-g.A, s, y[k]);
+        y[k] = mad(-g.A, s, y[k]);
     }
 }
 
@@ -317,14 +333,15 @@ __device__ __forceinline__ void volume_term(const RefOps<P>& R, double A, double
                                             double m11, const double (&pl)[RefOps<P>::NPHI],
                                             double (&y)[RefOps<P>::NPHI]) {
     constexpr int N = RefOps<P>::NPHI;
+    typedef double Real;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        double s0 = 0, s1 = 0, s2 = 0;
+        Real s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
         for (int l = 0; l < N; ++l) {
-            s0 = fma(R.S[0][k][l], pl[l], s0);
-            s1 = fma(R.S[1][k][l], pl[l], s1);
-            s2 = fma(R.S[2][k][l], pl[l], s2);
+            s0 = mad(R.S[0][k][l], pl[l], s0);
+            s1 = mad(R.S[1][k][l], pl[l], s1);
+            s2 = mad(R.S[2][k][l], pl[l], s2);
         }
         y[k] = -A * (m00 * s0 + m01 * s1 + m11 * s2);
     }

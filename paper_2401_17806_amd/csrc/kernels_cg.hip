@@ -63,33 +63,33 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
 
 // Dynamic LDS of k_cg_step, in doubles: sd [(T + hmax) N] directions d_k of the tile then of
 // its halo; sr [T N] residuals r_k of the tile; sm [T][3][N] per-lane partial rows.
-inline size_t step_lds_bytes(int nphi, int hmax) {
-    return sizeof(double) * (size_t)nphi * (size_t)(kTriPerBlock + hmax + kTriPerBlock +
-                                                    3 * kTriPerBlock);
+inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes) {
+    return real_bytes * (size_t)nphi * (size_t)(kTriPerBlock + hmax + kTriPerBlock +
+                                                3 * kTriPerBlock);
 }
 
-template <int P>
-__global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restrict__ ops,
+template <int P, typename Real, class Ops>
+__global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ ops,
                                                        const double4* __restrict__ geo,
                                                        const int4* __restrict__ nbr,
                                                        const int* __restrict__ halo_off,
                                                        const int* __restrict__ halo_ids, int hmax,
-                                                       int64_t ne, double* __restrict__ x,
-                                                       const double* __restrict__ r_in,
-                                                       const double* __restrict__ q_in,
-                                                       const double* __restrict__ d_in,
-                                                       double* __restrict__ r_out,
-                                                       double* __restrict__ q_out,
-                                                       double* __restrict__ d_out,
+                                                       int64_t ne, Real* __restrict__ x,
+                                                       const Real* __restrict__ r_in,
+                                                       const Real* __restrict__ q_in,
+                                                       const Real* __restrict__ d_in,
+                                                       Real* __restrict__ r_out,
+                                                       Real* __restrict__ q_out,
+                                                       Real* __restrict__ d_out,
                                                        const double* __restrict__ part_in,
                                                        double* __restrict__ part_out,
                                                        double* __restrict__ scal, int parity) {
     constexpr int N = RefOps<P>::NPHI;
     constexpr int T = kTriPerBlock;
-    extern __shared__ double lds[];
-    double* sd = lds;
-    double* sr = lds + (size_t)(T + hmax) * N;
-    double* sm = sr + (size_t)T * N;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Real* sd = reinterpret_cast<Real*>(lds_raw);
+    Real* sr = sd + (size_t)(T + hmax) * N;
+    Real* sm = sr + (size_t)T * N;
     if (scal[S::DONE] != 0.0) return;
     const int G = gridDim.x;
     const double it = scal[S::ITER0 + parity];
@@ -120,6 +120,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restri
         beta = rr_next / rr;
     }
     const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
+    const Real ra = (Real)alpha, rb = (Real)beta;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t tile = blockIdx.x; tile * T < ne; tile += G) {
         const int64_t i0 = tile * T;
@@ -128,22 +129,22 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restri
         // phase 1: state update of the tile (coalesced) and directions of tile + halo into LDS
         for (int f = threadIdx.x; f < nown; f += kBlockTri) {
             const int64_t o = base + f;
-            const double dprev = d_in[o];
-            const double rk = fma(-alpha, q_in[o], r_in[o]);
-            const double dk = fma(beta, dprev, rk);
-            x[o] = fma(alpha, dprev, x[o]);
+            const Real dprev = d_in[o];
+            const Real rk = mad(-ra, q_in[o], r_in[o]);
+            const Real dk = mad(rb, dprev, rk);
+            x[o] = mad(ra, dprev, x[o]);
             r_out[o] = rk;
             d_out[o] = dk;
             sd[f] = dk;
             sr[f] = rk;
-            acc[0] = fma(rk, rk, acc[0]);
+            acc[0] = fma((double)rk, (double)rk, acc[0]);
         }
         const int h0 = halo_off[tile];
         const int nh = (halo_off[tile + 1] - h0) * N;
         for (int e = threadIdx.x; e < nh; e += kBlockTri) {
             const int t = e / N;
             const int64_t o = (int64_t)halo_ids[h0 + t] * N + (e - t * N);
-            sd[T * N + e] = fma(beta, d_in[o], fma(-alpha, q_in[o], r_in[o]));
+            sd[T * N + e] = mad(rb, d_in[o], mad(-ra, q_in[o], r_in[o]));
         }
         __syncthreads();
         // phase 2: three lanes per triangle, operands from LDS
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restri
             const int4 nb4 = nbr[i];
             const int nb = pick(nb4, al);
             const int slot = (nb4.w >> (10 * al)) & 1023;
-            double pl[N], pr[N], y[N];
+            Real pl[N], pr[N], y[N];
 #pragma unroll
             for (int l = 0; l < N; ++l) pl[l] = sd[tl * N + rot_sel<P>(al, l)];
             int ar = 0;
@@ -164,9 +165,9 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restri
                 er = geo[nb >> 2];
             } else {
 #pragma unroll
-                for (int l = 0; l < N; ++l) pr[l] = 0.0;
+                for (int l = 0; l < N; ++l) pr[l] = Real(0);
             }
-            edge_lane_core<P>(al, *ops, geo[i], nb, ar, er, pl, pr, y);
+            edge_lane_core<P, Ops, Real>(al, *ops, geo[i], nb, ar, er, pl, pr, y);
 #pragma unroll
             for (int k = 0; k < N; ++k) sm[(tl * 3 + al) * N + rot_sel<P>(al, k)] = y[k];
         }
@@ -174,12 +175,12 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const RefOps<P>* __restri
         // phase 3: q_k = -K d_k (coalesced) and the dot products
         for (int f = threadIdx.x; f < nown; f += kBlockTri) {
             const int t = f / N, k = f - t * N;
-            const double qk = -(sm[(t * 3) * N + k] + sm[(t * 3 + 1) * N + k] + sm[(t * 3 + 2) * N + k]);
+            const Real qk = -(sm[(t * 3) * N + k] + sm[(t * 3 + 1) * N + k] + sm[(t * 3 + 2) * N + k]);
             q_out[base + f] = qk;
-            const double dk = sd[f], rk = sr[f];
-            acc[1] = fma(dk, qk, acc[1]);
-            acc[2] = fma(rk, qk, acc[2]);
-            acc[3] = fma(qk, qk, acc[3]);
+            const double dk = sd[f], rk = sr[f], qd = qk;
+            acc[1] = fma(dk, qd, acc[1]);
+            acc[2] = fma(rk, qd, acc[2]);
+            acc[3] = fma(qd, qd, acc[3]);
         }
         __syncthreads();
     }
@@ -468,8 +469,100 @@ __global__ __launch_bounds__(kBlockTri) void k_apply_internal(const RefOps<P>* _
         for (int k = al; k < N; k += 3) out[i * N + k] = sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k];
 }
 
+// ---------------------------------------------------------------- mixed precision
+// One FP32 Krylov process (the k_cg_step<float> iterations, with the correction accumulated in
+// e32) refreshed by FP64 "reliable updates": x += e (float64), r := K x - b recomputed in
+// float64 and rounded back to the FP32 residual, keeping the search direction.  All FP32
+// quantities are scaled by s = 1/||b_int|| so the tolerance is relative and FP32 stays in range.
+
+// one block: s from |b_int|^2 and the inner scalars
+__global__ __launch_bounds__(kBlockFlat) void k_rel_init(double* __restrict__ scal,
+                                                         double* __restrict__ scal_in, double rtol,
+                                                         int maxit) {
+    if (threadIdx.x == 0) {
+        const double bb = scal[S::BB];
+        scal[S::IRS] = bb > 0.0 ? 1.0 / sqrt(bb) : 0.0;
+        scal_in[S::DONE] = scal[S::DONE];  // zero right-hand side: nothing to do
+        scal_in[S::ITER] = 0.0;
+        scal_in[S::ITER0] = 0.0;
+        scal_in[S::ITER1] = 0.0;
+        scal_in[S::RR] = 0.0;
+        scal_in[S::TOL2] = rtol * rtol;  // relative: the scaled right-hand side has unit norm
+        scal_in[S::MAXIT] = (double)maxit;
+    }
+}
+
+// r32 = s r64; partials of r32.r32 and r32.q32 into the rr / rq slots of the current state
+// (dq and qq of that state are unchanged: d and q are kept).  init: also e = q = d = 0.
+__global__ __launch_bounds__(kBlockFlat) void k_rel_to32(int64_t n, const double* __restrict__ r64,
+                                                         const double* __restrict__ scal,
+                                                         float* __restrict__ r32,
+                                                         float* __restrict__ q32,
+                                                         float* __restrict__ d32,
+                                                         float* __restrict__ e, int init,
+                                                         double* __restrict__ part) {
+    const double sc = scal[S::IRS];
+    double acc[2] = {0.0, 0.0};
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        const float rv = (float)(sc * r64[t]);
+        r32[t] = rv;
+        if (init) {
+            e[t] = 0.0f;
+            q32[t] = 0.0f;
+            d32[t] = 0.0f;
+        }
+        const double rd = rv;
+        acc[0] = fma(rd, rd, acc[0]);
+        acc[1] = fma(rd, (double)q32[t], acc[1]);
+    }
+    block_sum_all<2, kBlockFlat>(acc);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc[0];                  // rr slot
+        part[2 * gridDim.x + blockIdx.x] = acc[1];  // rq slot
+    }
+}
+
+// x += e / s (float64); e = 0
+__global__ __launch_bounds__(kBlockFlat) void k_rel_accumulate(int64_t n, double* __restrict__ x,
+                                                               float* __restrict__ e,
+                                                               const double* __restrict__ scal) {
+    const double sc = scal[S::IRS];
+    const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        x[t] = fma((double)e[t], inv, x[t]);
+        e[t] = 0.0f;
+    }
+}
+
+// restart the FP32 Krylov process (after it stopped on its own criterion)
+__global__ void k_rel_restart(double* __restrict__ scal_in) {
+    if (threadIdx.x == 0) {
+        scal_in[S::DONE] = 0.0;
+        scal_in[S::ITER] = 0.0;
+        scal_in[S::ITER0] = 0.0;
+        scal_in[S::ITER1] = 0.0;
+    }
+}
+
+// one block: current recursive rr of the FP32 state (slot 0 of the partials) -> scal_in[RRNOW];
+// optionally clear the inner DONE flag (resume after a reliable update)
+__global__ __launch_bounds__(kBlockFlat) void k_rel_peek(const double* __restrict__ part, int nb,
+                                                         double* __restrict__ scal_in, int resume) {
+    const double rr = reduce_partials<kBlockFlat>(part, nb);
+    if (threadIdx.x == 0) {
+        scal_in[S::RRNOW] = rr;
+        if (resume) scal_in[S::DONE] = 0.0;
+    }
+}
+
 template <int P>
 const RefOps<P>* ops_of(const sld_disc_s* d) { return reinterpret_cast<const RefOps<P>*>(d->ops_dev); }
+template <int P>
+const RefOps32<P>* ops32_of(const sld_disc_s* d) {
+    return reinterpret_cast<const RefOps32<P>*>(d->ops32_dev);
+}
 
 #define SLD_DISPATCH(p, CALL)                                   \
     switch (p) {                                                \
@@ -517,8 +610,8 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
                                               w.scal, parity));
         return hipGetLastError();
     }
-    const size_t lds = step_lds_bytes(d->nphi, m->hmax);
-    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_step<PP>, dim3(G), dim3(kBlockTri), lds, s,
+    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double));
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>>), dim3(G), dim3(kBlockTri), lds, s,
                                           ops_of<PP>(d), m->geo_i, m->nbr_i, m->halo_off,
                                           m->halo_ids, m->hmax, m->ne, w.x, w.r[parity], w.q[parity],
                                           w.d[parity], w.r[o], w.q[o], w.d[o],
@@ -549,5 +642,55 @@ hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s) {
     const int64_t n = m->ne * d->nphi;
     hipLaunchKernelGGL(k_gauge_out, dim3(G), dim3(kBlockFlat), 0, s, n, d->nphi, m->perm, w.x,
                        w.scal, 1.0 / m->area_total, p_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    const CgWork& w = d->cg;
+    const int G = w.grid;
+    const int o = 1 - parity;
+    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float));
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>>), dim3(G),
+                                          dim3(kBlockTri), lds, s, ops32_of<PP>(d), m->geo_i,
+                                          m->nbr_i, m->halo_off, m->halo_ids, m->hmax, m->ne, w.e32,
+                                          w.r32[parity], w.q32[parity], w.d32[parity], w.r32[o],
+                                          w.q32[o], w.d32[o], w.part32 + parity * 4 * G,
+                                          w.part32 + o * 4 * G, w.scal_in, parity));
+    return hipGetLastError();
+}
+
+// mixed-precision setup: the FP64 setup left r64 = K x - b_int in w.r[0]
+hipError_t launch_rel_init(const sld_disc_s* d, double rtol, int maxit, hipStream_t s) {
+    const CgWork& w = d->cg;
+    const int64_t n = d->mesh->ne * d->nphi;
+    hipLaunchKernelGGL(k_rel_init, dim3(1), dim3(kBlockFlat), 0, s, w.scal, w.scal_in, rtol, maxit);
+    hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
+                       w.q32[0], w.d32[0], w.e32, 1, w.part32);
+    return hipGetLastError();
+}
+
+// reliable update on the current state (buffers 0 after an even number of iterations):
+// x += e; r64 = K x - b_int (float64, partials -> part_s, |r64|^2 -> scal[RR]); r32 = s r64
+hipError_t launch_rel_update(const sld_disc_s* d, int restart, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    const CgWork& w = d->cg;
+    const int64_t n = m->ne * d->nphi;
+    hipLaunchKernelGGL(k_rel_accumulate, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.x, w.e32, w.scal);
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(w.grid), dim3(kBlockTri), 0, s,
+                                          ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
+                                          w.r[0], w.part_s, w.scal));
+    hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal,
+                       (int)S::RR, 1.0);
+    hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
+                       w.q32[0], w.d32[0], w.e32, restart, w.part32);
+    if (restart) hipLaunchKernelGGL(k_rel_restart, dim3(1), dim3(64), 0, s, w.scal_in);
+    return hipGetLastError();
+}
+
+hipError_t launch_rel_peek(const sld_disc_s* d, int resume, hipStream_t s) {
+    const CgWork& w = d->cg;
+    hipLaunchKernelGGL(k_rel_peek, dim3(1), dim3(kBlockFlat), 0, s, w.part32, w.grid, w.scal_in,
+                       resume);
     return hipGetLastError();
 }

@@ -38,6 +38,42 @@ struct RefOps {
     double w[NPHI];
 };
 
+// Float copy of the operators the Schur apply uses (mixed-precision inner solves).
+template <int P>
+struct RefOps32 {
+    static constexpr int NPHI = RefOps<P>::NPHI;
+    static constexpr int NE = P + 1;
+    float S[3][NPHI][NPHI];
+    float Sh[3][3][NPHI][NPHI];
+    float E[3][2][NE][NPHI];
+    float Pt[3][2][NPHI][NE];
+    float C[NE][NE];
+    float M1[NE][NE];
+};
+
+template <int P>
+void round_refops(const RefOps<P>& in, RefOps32<P>* out) {
+    constexpr int N = RefOps<P>::NPHI, NE = P + 1;
+    for (int t = 0; t < 3; ++t)
+        for (int k = 0; k < N; ++k)
+            for (int l = 0; l < N; ++l) {
+                out->S[t][k][l] = (float)in.S[t][k][l];
+                for (int a = 0; a < 3; ++a) out->Sh[a][t][k][l] = (float)in.Sh[a][t][k][l];
+            }
+    for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 2; ++d) {
+            for (int m = 0; m < NE; ++m)
+                for (int l = 0; l < N; ++l) out->E[a][d][m][l] = (float)in.E[a][d][m][l];
+            for (int k = 0; k < N; ++k)
+                for (int m = 0; m < NE; ++m) out->Pt[a][d][k][m] = (float)in.Pt[a][d][k][m];
+        }
+    for (int m = 0; m < NE; ++m)
+        for (int q = 0; q < NE; ++q) {
+            out->C[m][q] = (float)in.C[m][q];
+            out->M1[m][q] = (float)in.M1[m][q];
+        }
+}
+
 // Fill ops for degree P (1..4).  Returns 0 on success.
 template <int P>
 int build_refops(RefOps<P>* ops);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -31,6 +32,7 @@ constexpr int kSlotWall = 1023;  // tile-local slot of a wall neighbour
 inline int32_t pack_nbr(int32_t tri, int32_t alpha) { return tri < 0 ? -1 : (tri << 2) | alpha; }
 
 struct sld_mesh_s {
+    std::atomic<int> refs{1};  // the caller's handle + one per disc built on the mesh
     int device = 0;
     int64_t ne = 0, nd = 0, nv = 0;
     bool periodic = false;
@@ -74,6 +76,16 @@ struct CgWork {
     int grid = 0;                  // blocks of every CG kernel
     bool wave_kernel = false;      // iteration kernel variant (by mesh size)
     std::vector<hipEvent_t> events;  // profiling events (created on first profiled solve)
+    // mixed precision: FP32 inner CG state (e32 = the correction), its partials and scalars
+    float* r32[2] = {nullptr, nullptr};
+    float* q32[2] = {nullptr, nullptr};
+    float* d32[2] = {nullptr, nullptr};
+    float* e32 = nullptr;
+    double* part32 = nullptr;      // [2][4][grid]
+    double* scal_in = nullptr;     // inner-solve scalars (CgScalars)
+    double* host_scal_in = nullptr;
+    hipGraphExec_t graph32 = nullptr;
+    int graph32_block = 0;
     hipStream_t capture = nullptr;   // private stream used to capture the iteration graph
     hipGraphExec_t graph = nullptr;  // captured block of iterations
     int graph_block = 0;             // iterations in `graph`
@@ -84,11 +96,14 @@ struct sld_disc_s {
     int p = 0, nphi = 0, npsi = 0;
     void* ops_dev = nullptr;       // RefOps<p> on the device
     void* ops_host = nullptr;      // RefOps<p> on the host
+    void* ops32_dev = nullptr;     // RefOps32<p> on the device (mixed precision)
     size_t ops_bytes = 0;
     CgWork cg;
 };
 
-// Kernel launchers (kernels.hip).  All return hipError_t of the launch.
+uint64_t sld_disc_bytes(const sld_disc_s* d);
+
+// Kernel launchers (kernels_ops.hip, kernels_cg.hip).  All return hipError_t of the launch.
 hipError_t launch_schur_apply(const sld_disc_s* d, const double* p, double* out, double scale,
                               hipStream_t s);
 hipError_t launch_gradient(const sld_disc_s* d, const double* p, const double* vstar, double coef,
@@ -100,10 +115,14 @@ hipError_t launch_divergence(const sld_disc_s* d, const double* v, double scale,
 struct CgScalars {
     // layout of CgWork::scal (doubles)
     enum { RR = 0, BB = 1, TOL2 = 2, ITER = 3, DONE = 4, MAXIT = 5, MEAN = 6, ZERO = 7,
-           RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, NSCAL = 16 };
+           RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, IRS = 12, RRNOW = 13, NSCAL = 16 };
 };
 int cg_grid_for(int64_t ne, bool wave_kernel);
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
                            double rtol, int maxit, hipStream_t s);
 hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s);
 hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s);
+hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s);
+hipError_t launch_rel_init(const sld_disc_s* d, double rtol, int maxit, hipStream_t s);
+hipError_t launch_rel_update(const sld_disc_s* d, int restart, hipStream_t s);
+hipError_t launch_rel_peek(const sld_disc_s* d, int resume, hipStream_t s);

@@ -13,6 +13,9 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: its HIP runtime is then the one libsld.so binds to, so the streams and device
+# pointers torch hands over belong to the same runtime as the library's own calls
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsld.so")
@@ -32,14 +35,15 @@ _i32 = ctypes.c_int32
 
 
 class sld_cg_params(ctypes.Structure):
-    _fields_ = [("rtol", ctypes.c_double), ("maxit", _i32), ("warm_start", _i32),
-                ("graph_block", _i32), ("profile", _i32), ("reserved", _i32)]
+    _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("maxit", _i32),
+                ("warm_start", _i32), ("graph_block", _i32), ("profile", _i32),
+                ("precision", _i32), ("max_outer", _i32)]
 
 
 class sld_cg_report(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged", _i32), ("rel_res", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("step_us", ctypes.c_double), ("timed_iters", _i32), ("reserved", _i32)]
+                ("step_us", ctypes.c_double), ("timed_iters", _i32), ("outer_iters", _i32)]
 
 
 def _sig(name, args, res=ctypes.c_int):
@@ -69,12 +73,23 @@ _sig("sld_pressure_rhs", [_vp, _vp, ctypes.c_double, _vp, _vp])
 _sig("sld_velocity_correct", [_vp, _vp, _vp, ctypes.c_double, _vp, _vp])
 _sig("sld_cg_solve", [_vp, _vp, _vp, ctypes.POINTER(sld_cg_params),
                       ctypes.POINTER(sld_cg_report), _vp])
+_sig("sld_disc_footprint", [_vp, ctypes.POINTER(ctypes.c_uint64)])
+_sig("sld_server_create", [_i32, ctypes.c_uint64, _i32, ctypes.POINTER(_vp)])
+_sig("sld_server_submit", [_vp, _vp, _vp, _vp, ctypes.POINTER(sld_cg_params), _vp,
+                           ctypes.POINTER(ctypes.c_uint64)])
+_sig("sld_server_poll", [_vp, ctypes.c_uint64, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                         ctypes.POINTER(sld_cg_report)])
+_sig("sld_server_stats", [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)])
+_sig("sld_server_destroy", [_vp], None)
 
 EXPORTED = [
     "sld_last_error", "sld_abi_version", "sld_mesh_create", "sld_mesh_counts", "sld_mesh_edges",
     "sld_mesh_destroy", "sld_disc_create", "sld_disc_info", "sld_main_nodes", "sld_dual_nodes",
     "sld_main_weights", "sld_disc_destroy", "sld_schur_apply", "sld_gradient", "sld_divergence",
-    "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve",
+    "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_disc_footprint",
+    "sld_server_create", "sld_server_submit", "sld_server_poll", "sld_server_stats",
+    "sld_server_destroy",
 ]
 
 STATUS = {0: "SLD_OK", 1: "SLD_E_INVALID", 2: "SLD_E_MESH", 3: "SLD_E_NOMEM", 4: "SLD_E_HIP",
@@ -155,6 +170,22 @@ def sld_disc_info(h):
 
 def sld_disc_destroy(h):
     _lib.sld_disc_destroy(h)
+
+
+def make_params(rtol=1e-12, maxit=100000, warm_start=False, graph_block=32, profile=False,
+                precision="fp64", inner_rtol=0.5, max_outer=1000):
+    if precision not in ("fp64", "mixed"):
+        raise ValueError("precision must be 'fp64' or 'mixed'")
+    return sld_cg_params(float(rtol), float(inner_rtol), int(maxit), int(bool(warm_start)),
+                         int(graph_block), int(bool(profile)), 1 if precision == "mixed" else 0,
+                         int(max_outer))
+
+
+def report_dict(rep, st):
+    return {"iters": rep.iters, "converged": bool(rep.converged), "rel_res": rep.rel_res,
+            "rel_res_true": rep.rel_res_true, "seconds": rep.seconds, "step_us": rep.step_us,
+            "timed_iters": rep.timed_iters, "outer_iters": rep.outer_iters,
+            "status": STATUS.get(st, st)}
 
 
 class Mesh:
@@ -259,19 +290,23 @@ class Disc:
                                          self._dev(out, self.dual_shape, "v"), self._stream(stream)))
         return out
 
+    def footprint(self) -> int:
+        v = ctypes.c_uint64()
+        _check(_lib.sld_disc_footprint(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
     def sld_cg_solve(self, b, p=None, rtol=1e-12, maxit=100000, warm_start=False,
-                     graph_block=32, profile=False, stream=None):
+                     graph_block=32, profile=False, precision="fp64", inner_rtol=0.5,
+                     max_outer=1000, stream=None):
+        """Solve K p = b (gauge int p = 0).  precision: "fp64" or "mixed"."""
         p = self._new(self.main_shape) if p is None else p
-        prm = sld_cg_params(float(rtol), int(maxit), int(bool(warm_start)), int(graph_block),
-                            int(bool(profile)), 0)
+        prm = make_params(rtol, maxit, warm_start, graph_block, profile, precision, inner_rtol,
+                          max_outer)
         rep = sld_cg_report()
         st = _lib.sld_cg_solve(self.handle, self._dev(b, self.main_shape, "b"),
                                self._dev(p, self.main_shape, "p"), ctypes.byref(prm),
                                ctypes.byref(rep), self._stream(stream))
-        report = {"iters": rep.iters, "converged": bool(rep.converged), "rel_res": rep.rel_res,
-                  "rel_res_true": rep.rel_res_true, "seconds": rep.seconds,
-                  "step_us": rep.step_us,
-                  "timed_iters": rep.timed_iters, "status": STATUS.get(st, st)}
+        report = report_dict(rep, st)
         if st not in (0, 5):
             _check(st)
         return p, report
@@ -280,6 +315,56 @@ class Disc:
         if getattr(self, "handle", None):
             sld_disc_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Owner of an sld_server handle (continuous batching of solves, see include/sld.h)."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 16 << 30, workers: int = 4):
+        self.device = int(device)
+        self.handle = _vp()
+        _check(_lib.sld_server_create(self.device, int(budget_bytes), int(workers),
+                                      ctypes.byref(self.handle)))
+        self._keep = {}
+
+    def sld_server_submit(self, disc: Disc, b, p, stream=None, **params):
+        prm = make_params(**params)
+        t = ctypes.c_uint64()
+        _check(_lib.sld_server_submit(self.handle, disc.handle, disc._dev(b, disc.main_shape, "b"),
+                                      disc._dev(p, disc.main_shape, "p"), ctypes.byref(prm),
+                                      disc._stream(stream), ctypes.byref(t)))
+        self._keep[t.value] = (b, p)  # buffers stay alive until the ticket completes
+        return t.value
+
+    def sld_server_poll(self, ticket: int, wait: bool = False):
+        done, st = _i32(), _i32()
+        rep = sld_cg_report()
+        _check(_lib.sld_server_poll(self.handle, ctypes.c_uint64(ticket), int(bool(wait)),
+                                    ctypes.byref(done), ctypes.byref(st), ctypes.byref(rep)))
+        if not done.value:
+            return None
+        self._keep.pop(ticket, None)
+        return report_dict(rep, st.value)
+
+    def sld_server_stats(self):
+        q, r = _i32(), _i32()
+        b, c = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.sld_server_stats(self.handle, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b),
+                                     ctypes.byref(c)))
+        return {"queued": q.value, "running": r.value, "in_flight_bytes": b.value,
+                "completed": c.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.sld_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -190,3 +190,23 @@ def test_host_checks_reject_bad_buffers(torch_dev):
     x = torch.zeros(mesh.ne, disc.nphi, dtype=torch.float64, device="cuda:0")
     with pytest.raises(sld.SldError):
         disc.sld_schur_apply(x, out=x)
+
+
+@pytest.mark.parametrize("n,p,periodic", [(8, 1, True), (8, 2, True), (12, 3, True), (8, 4, True),
+                                          (7, 3, False)])
+def test_mixed_precision_solution_parity(torch_dev, n, p, periodic):
+    """Mixed form: one FP32 CG process refreshed by FP64 reliable updates reaches the FP64
+    oracle's solution within 1e-9 (relative L2, both gauged)."""
+    torch = torch_dev
+    _say(f"[cg mixed] n={n} p={p} periodic={periodic}")
+    od, K, mesh, disc = _setup(n, p, periodic)
+    f = random_fourier_field(17, kmax=4, length=(2 * np.pi if periodic else 1.0))
+    b = solve.divergence(od, f(od.dual_node_xy()).transpose(0, 2, 1))
+    x_or, info = solve.cg(K, b, tol=1e-13)
+    x_or = solve.gauge(od, x_or)
+    p_gpu, rep = disc.sld_cg_solve(_to(torch, b), rtol=1e-11, precision="mixed", inner_rtol=0.3,
+                                   maxit=20000, graph_block=8)
+    _say("   report", rep)
+    assert rep["outer_iters"] >= 1
+    assert rep["rel_res_true"] < 1e-10
+    assert _rel(p_gpu.cpu().numpy(), x_or) <= SOLVE_TOL

@@ -82,3 +82,18 @@ def test_host_only_handle_refuses_device_work():
     d = sld.Disc(m, 2)
     st = sld._lib.sld_schur_apply(d.handle, ctypes.c_void_p(8), ctypes.c_void_p(16), None)
     assert st == 1 and "host-only" in sld.sld_last_error()
+
+
+def test_disc_keeps_its_mesh_alive():
+    """Destroying the mesh handle first (as a garbage collector may) leaves the disc usable;
+    the mesh is freed with the last disc."""
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(5, seed=2)
+    m = sld.Mesh(xy, tri, per, device=-1)
+    d1, d2 = sld.Disc(m, 2), sld.Disc(m, 3)
+    want = d1.main_nodes().copy()
+    m.close()
+    assert np.array_equal(d1.main_nodes(), want)
+    d1.close()
+    assert d2.dual_nodes().shape[0] == 3 * 25
+    d2.close()
