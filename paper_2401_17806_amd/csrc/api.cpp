@@ -867,22 +867,23 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
     } else {
         // FP32 CG with FP64 reliable updates.  The setup left r64 = K x - b_int (partials in
         // part_s); one Krylov process runs in FP32 and is refreshed in FP64 whenever its
-        // residual has dropped by `refresh` since the last refresh, and when it believes it
-        // has converged (the FP64 residual then decides).
+        // residual has dropped by `refresh` since the last refresh, and when it stops on its own
+        // criterion (the FP64 residual then decides).  A refresh keeps the search direction
+        // while the recursive FP32 residual still tracks the true one (relative gap <= kGapMax);
+        // beyond that the kept direction is no longer conjugate to the new residual and the
+        // FP32 process restarts from it.
+        constexpr double kGapMax = 0.3;
         const double refresh = prm->inner_rtol;
         int total = 0, base = 0;
         SLD_HIP_CHECK(launch_rel_init(d, prm->rtol, prm->maxit, s));
         double rr_ref = 1.0;   // scaled rr at the last refresh
-        double prev64 = -1.0;  // FP64 rr at the previous restart
-        double last64 = -1.0;  // FP64 rr at the previous refresh
+        double prev64 = -1.0;  // FP64 rr when the FP32 process last stopped on its own
         while (true) {
-            // graph blocks of FP32 iterations until the residual has dropped by `refresh`
-            // since the last refresh, or the FP32 process stops on its own criterion
             IterStats in;
             while (true) {
                 sld_status e = run_block(d, prm->graph_block, s, &in);
                 if (e != SLD_OK) return e;
-                if (in.done) break;
+                if (in.done || base + in.iters >= prm->maxit) break;
                 SLD_HIP_CHECK(launch_rel_peek(d, 0, s));
                 SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal_in, w.scal_in, S::NSCAL * sizeof(double),
                                              hipMemcpyDeviceToHost, s));
@@ -890,10 +891,7 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
                 if (w.host_scal_in[S::RRNOW] <= refresh * refresh * rr_ref) break;
             }
             total = base + in.iters;
-            // reliable update in float64 (a restart of the FP32 process if it had stopped)
-            const int restart = in.done != 0;
-            if (restart) base = total;
-            SLD_HIP_CHECK(launch_rel_update(d, restart, s));
+            SLD_HIP_CHECK(launch_rel_update(d, s));
             SLD_HIP_CHECK(launch_rel_peek(d, 0, s));
             SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
                                          hipMemcpyDeviceToHost, s));
@@ -908,15 +906,16 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
                 status = 1;
                 break;
             }
-            if (!std::isfinite(rr)) {
+            if (!std::isfinite(rr) || !std::isfinite(rr_ref)) {
                 status = 3;
                 break;
             }
-            if (in.done == 2 || outer >= prm->max_outer) {
+            if (in.done == 2 || total >= prm->maxit || outer >= prm->max_outer) {
                 status = 2;
                 break;
             }
-            if (restart) {
+            bool restart = w.host_scal_in[S::GAP] > kGapMax * kGapMax * rr_ref;
+            if (in.done) {
                 // the FP32 process met rtol but the FP64 residual did not: go on from the
                 // refreshed residual unless the FP64 residual has stopped improving (floor)
                 if (prev64 >= 0 && rr > 0.25 * prev64) {
@@ -924,18 +923,12 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
                     break;
                 }
                 prev64 = rr;
-            } else if (last64 >= 0 && rr > last64) {
-                // the FP64 residual grew since the previous refresh: the FP32 directions have
-                // lost conjugacy; restart the FP32 process from the current solution
-                base = total;
-                SLD_HIP_CHECK(launch_rel_update(d, 1, s));
-                SLD_HIP_CHECK(launch_rel_peek(d, 0, s));
-                SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal_in, w.scal_in, S::NSCAL * sizeof(double),
-                                             hipMemcpyDeviceToHost, s));
-                SLD_HIP_CHECK(hipStreamSynchronize(s));
-                rr_ref = w.host_scal_in[S::RRNOW];
+                restart = true;
             }
-            last64 = rr;
+            if (restart) {
+                base = total;
+                SLD_HIP_CHECK(launch_rel_restart(d, s));
+            }
         }
         st.iters = total;
     }

@@ -493,19 +493,23 @@ __global__ __launch_bounds__(kBlockFlat) void k_rel_init(double* __restrict__ sc
 }
 
 // r32 = s r64; partials of r32.r32 and r32.q32 into the rr / rq slots of the current state
-// (dq and qq of that state are unchanged: d and q are kept).  init: also e = q = d = 0.
+// (dq and qq of that state are unchanged: d and q are kept), and of |s r64 - r32_old|^2 (the gap
+// between the refreshed and the recursive FP32 residual) into gap_part.  init: also e = q = d = 0.
 __global__ __launch_bounds__(kBlockFlat) void k_rel_to32(int64_t n, const double* __restrict__ r64,
                                                          const double* __restrict__ scal,
                                                          float* __restrict__ r32,
                                                          float* __restrict__ q32,
                                                          float* __restrict__ d32,
                                                          float* __restrict__ e, int init,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part,
+                                                         double* __restrict__ gap_part) {
     const double sc = scal[S::IRS];
-    double acc[2] = {0.0, 0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * kBlockFlat) {
-        const float rv = (float)(sc * r64[t]);
+        const double rt = sc * r64[t];
+        const float rv = (float)rt;
+        const double g = rt - (double)r32[t];
         r32[t] = rv;
         if (init) {
             e[t] = 0.0f;
@@ -515,11 +519,13 @@ __global__ __launch_bounds__(kBlockFlat) void k_rel_to32(int64_t n, const double
         const double rd = rv;
         acc[0] = fma(rd, rd, acc[0]);
         acc[1] = fma(rd, (double)q32[t], acc[1]);
+        acc[2] = fma(g, g, acc[2]);
     }
-    block_sum_all<2, kBlockFlat>(acc);
+    block_sum_all<3, kBlockFlat>(acc);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = acc[0];                  // rr slot
         part[2 * gridDim.x + blockIdx.x] = acc[1];  // rq slot
+        gap_part[blockIdx.x] = acc[2];
     }
 }
 
@@ -666,13 +672,14 @@ hipError_t launch_rel_init(const sld_disc_s* d, double rtol, int maxit, hipStrea
     const int64_t n = d->mesh->ne * d->nphi;
     hipLaunchKernelGGL(k_rel_init, dim3(1), dim3(kBlockFlat), 0, s, w.scal, w.scal_in, rtol, maxit);
     hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
-                       w.q32[0], w.d32[0], w.e32, 1, w.part32);
+                       w.q32[0], w.d32[0], w.e32, 1, w.part32, w.part_s);
     return hipGetLastError();
 }
 
 // reliable update on the current state (buffers 0 after an even number of iterations):
-// x += e; r64 = K x - b_int (float64, partials -> part_s, |r64|^2 -> scal[RR]); r32 = s r64
-hipError_t launch_rel_update(const sld_disc_s* d, int restart, hipStream_t s) {
+// x += e; r64 = K x - b_int (float64, |r64|^2 -> scal[RR]); r32 = s r64, keeping d and q;
+// |s r64 - r32_recursive|^2 -> scal_in[GAP]
+hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     const CgWork& w = d->cg;
     const int64_t n = m->ne * d->nphi;
@@ -683,8 +690,20 @@ hipError_t launch_rel_update(const sld_disc_s* d, int restart, hipStream_t s) {
     hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal,
                        (int)S::RR, 1.0);
     hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
-                       w.q32[0], w.d32[0], w.e32, restart, w.part32);
-    if (restart) hipLaunchKernelGGL(k_rel_restart, dim3(1), dim3(64), 0, s, w.scal_in);
+                       w.q32[0], w.d32[0], w.e32, 0, w.part32, w.part_s);
+    hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal_in,
+                       (int)S::GAP, 1.0);
+    return hipGetLastError();
+}
+
+// restart the FP32 Krylov process from the refreshed residual: d = q = 0 (the next iteration
+// takes d = r), iteration counters and the stop flag cleared
+hipError_t launch_rel_restart(const sld_disc_s* d, hipStream_t s) {
+    const CgWork& w = d->cg;
+    const int64_t n = d->mesh->ne * d->nphi;
+    hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
+                       w.q32[0], w.d32[0], w.e32, 1, w.part32, w.part_s);
+    hipLaunchKernelGGL(k_rel_restart, dim3(1), dim3(64), 0, s, w.scal_in);
     return hipGetLastError();
 }
 

@@ -115,7 +115,7 @@ hipError_t launch_divergence(const sld_disc_s* d, const double* v, double scale,
 struct CgScalars {
     // layout of CgWork::scal (doubles)
     enum { RR = 0, BB = 1, TOL2 = 2, ITER = 3, DONE = 4, MAXIT = 5, MEAN = 6, ZERO = 7,
-           RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, IRS = 12, RRNOW = 13, NSCAL = 16 };
+           RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, IRS = 12, RRNOW = 13, GAP = 14, NSCAL = 16 };
 };
 int cg_grid_for(int64_t ne, bool wave_kernel);
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
@@ -124,5 +124,6 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s);
 hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s);
 hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s);
 hipError_t launch_rel_init(const sld_disc_s* d, double rtol, int maxit, hipStream_t s);
-hipError_t launch_rel_update(const sld_disc_s* d, int restart, hipStream_t s);
+hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s);
+hipError_t launch_rel_restart(const sld_disc_s* d, hipStream_t s);
 hipError_t launch_rel_peek(const sld_disc_s* d, int resume, hipStream_t s);
