@@ -28,6 +28,7 @@ WORKLOADS = {
     "tgv16_p2": dict(n=16, p=2, seed=1, rhs_seed=101),
     "tgv128_p3": dict(n=128, p=3, seed=2, rhs_seed=102),
     "tgv512_p3": dict(n=512, p=3, seed=3, rhs_seed=103),
+    "mix256_p4": dict(n=256, p=4, seed=1005, rhs_seed=1005),
 }
 DEFAULT = "tgv128_p3"
 HBM_PEAK_GBS = 8000.0
@@ -87,6 +88,13 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-12)
     ap.add_argument("--graph-block", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--timing", choices=("events", "graph"), default="events",
+                    help="events: every CG iteration launched directly and bracketed by HIP "
+                         "events on the solve stream (per-kernel durations); graph: captured "
+                         "graph blocks, per-iteration time from the solve's wall clock")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the measurement, copy MIB MiB device-to-device three times "
+                         "(reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the "
@@ -127,7 +135,7 @@ def main():
     reps = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        reps.append(step(profile=True))
+        reps.append(step(profile=args.timing == "events"))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -138,8 +146,11 @@ def main():
     div0 = disc.sld_divergence(vstar)
     divfree = float(torch.linalg.norm(div) / torch.linalg.norm(div0))
 
-    timed = sum(r["timed_iters"] for r in reps)
-    step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
+    if args.timing == "events":
+        timed = sum(r["timed_iters"] for r in reps)
+        step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
+    else:
+        step_us = 1e6 * sum(r["seconds"] for r in reps) / max(iters, 1)
     sbytes = step_bytes_per_tri(nphi) * ne
     achieved = sbytes / (step_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -175,6 +186,14 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, xy, tri, per, b.cpu().numpy())
     print(json.dumps(out), flush=True)
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy calibration: 3 x {nbytes} bytes read and written", file=sys.stderr)
 
 
 if __name__ == "__main__":

@@ -538,14 +538,10 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     DeviceGuard dg(m->device);
     const size_t nv = size_t(m->ne) * d->nphi;
     CgWork& w = d->cg;
-    const char* force = std::getenv("SLD_CG_KERNEL");  // debugging aid: "wave" or "lanes"
-    w.wave_kernel = m->ne >= kWaveKernelMinTri;
-    if (force && std::strcmp(force, "wave") == 0) w.wave_kernel = true;
-    if (force && std::strcmp(force, "lanes") == 0) w.wave_kernel = false;
-    int G = cg_grid_for(m->ne, w.wave_kernel);
+    int G = cg_grid_for(d);
     if (const char* gcap = std::getenv("SLD_CG_GRID")) {  // debugging aid: grid size cap
         const int cap = std::atoi(gcap);
-        if (cap > 0 && cap < G) G = cap;
+        if (cap > 0 && cap < G) G = (cap + 7) & ~7;
     }
     w.grid = G;
     std::lock_guard<std::mutex> lk(device_setup_mutex());

@@ -121,17 +121,6 @@ struct LoadPlain {
     __device__ __forceinline__ double at(int64_t t, int l) const { return src[t * N + l]; }
 };
 
-// CG direction: r + beta d_old
-template <int N>
-struct LoadDir {
-    const double* __restrict__ r;
-    const double* __restrict__ d;
-    double beta;
-    __device__ __forceinline__ double at(int64_t t, int l) const {
-        return fma(beta, d[t * N + l], r[t * N + l]);
-    }
-};
-
 // Core of lane `al` of a triangle: contributions to (K p)_i in the frame relabelled by al.
 // pl holds p_i in that frame, pr the neighbour's DOFs in the neighbour's frame relabelled by
 // ar (its shared edge is its local edge 0); e / er are the two triangles' edge vectors; nb < 0
@@ -245,113 +234,6 @@ __device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, 
         }
         y[k] = mad(-g.A, s, y[k]);
     }
-}
-
-// Edge AL (compile time) of a triangle in its own frame, one lane per triangle: adds the
-// dual-coupling terms of that edge to y (natural row numbering).  pl = p of the triangle,
-// pr = the neighbour's DOFs in the neighbour's frame relabelled by ar, er = its edge vectors,
-// nb < 0 = wall edge.
-template <int P, int AL>
-__device__ __forceinline__ void edge_term(const RefOps<P>& R, const Geo& g, double4 e, double m00,
-                                          double m01, double m11, int nb, int ar, double4 er,
-                                          const double (&pl)[RefOps<P>::NPHI],
-                                          const double (&pr)[RefOps<P>::NPHI],
-                                          double (&y)[RefOps<P>::NPHI]) {
-    constexpr int N = RefOps<P>::NPHI;
-    constexpr int NE = P + 1;
-    typedef double Real;
-    const double ex = AL == 0 ? e.x : (AL == 1 ? e.z - e.x : -e.z);
-    const double ey = AL == 0 ? e.y : (AL == 1 ? e.w - e.y : -e.w);
-    const double snx = ey, sny = -ex;  // |Gamma| n, outward
-    if (nb < 0) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            Real s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-            for (int l = 0; l < N; ++l) {
-                s0 = mad(R.Sh[AL][0][k][l], pl[l], s0);
-                s1 = mad(R.Sh[AL][1][k][l], pl[l], s1);
-                s2 = mad(R.Sh[AL][2][k][l], pl[l], s2);
-            }
-            y[k] += g.A * (m00 * s0 + m01 * s1 + m11 * s2);
-        }
-        return;
-    }
-    double f1x, f1y, f2x, f2y;
-    relabel(er, ar, f1x, f1y, f2x, f2y);
-    const Geo grd = make_geo(f1x, f1y, f2x, f2y);
-    const GeoR<Real> gr(grd);
-    const Real wsum = (Real)(1.0 / (g.A + grd.A));
-    Real delta[NE];
-#pragma unroll
-    for (int m = 0; m < NE; ++m) delta[m] = pr[P - m] - pl[edge_node(P, AL, m)];
-    Real gd0[NE], gd1[NE], tn[NE];
-#pragma unroll
-    for (int m = 0; m < NE; ++m) {
-        Real ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            ds0 = mad(R.E[AL][0][m][l], pl[l], ds0);
-            ds1 = mad(R.E[AL][1][m][l], pl[l], ds1);
-            dn0 = mad(R.E[0][0][P - m][l], pr[l], dn0);
-            dn1 = mad(R.E[0][1][P - m][l], pr[l], dn1);
-        }
-        const Real gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
-        const Real gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
-        Real cd = 0;
-#pragma unroll
-        for (int q = 0; q < NE; ++q) cd = mad(R.C[m][q], delta[q], cd);
-        const Real hx = (g.A * gsx + gr.A * gnx + Real(3) * snx * cd) * wsum;
-        const Real hy = (g.A * gsy + gr.A * gny + Real(3) * sny * cd) * wsum;
-        tn[m] = snx * hx + sny * hy;
-        const Real dx = hx - gsx, dy = hy - gsy;
-        gd0[m] = g.G00 * dx + g.G01 * dy;
-        gd1[m] = g.G10 * dx + g.G11 * dy;
-    }
-#pragma unroll
-    for (int m = 0; m < NE; ++m) {
-        Real s = 0;
-#pragma unroll
-        for (int q = 0; q < NE; ++q) s = mad(R.M1[m][q], tn[q], s);
-        y[edge_node(P, AL, m)] += s;
-    }
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        Real s = 0;
-#pragma unroll
-        for (int m = 0; m < NE; ++m) {
-            s = mad(R.Pt[AL][0][k][m], gd0[m], s);
-            s = mad(R.Pt[AL][1][k][m], gd1[m], s);
-        }
-        y[k] = mad(-g.A, s, y[k]);
-    }
-}
-
-// Whole-triangle volume term y = -A (m00 S0 + m01 S1 + m11 S2) p (natural rows).
-template <int P>
-__device__ __forceinline__ void volume_term(const RefOps<P>& R, double A, double m00, double m01,
-                                            double m11, const double (&pl)[RefOps<P>::NPHI],
-                                            double (&y)[RefOps<P>::NPHI]) {
-    constexpr int N = RefOps<P>::NPHI;
-    typedef double Real;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        Real s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            s0 = mad(R.S[0][k][l], pl[l], s0);
-            s1 = mad(R.S[1][k][l], pl[l], s1);
-            s2 = mad(R.S[2][k][l], pl[l], s2);
-        }
-        y[k] = -A * (m00 * s0 + m01 * s1 + m11 * s2);
-    }
-}
-
-// Wave-scope LDS ordering: stores of this wave are complete and visible to its own lanes
-// before later LDS reads (and the compiler does not move LDS accesses across it).
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
 }
 
 // Lane `al` of triangle i with p read through a loader (global memory).

@@ -61,6 +61,27 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
     if (threadIdx.x == 0) part_out[blockIdx.x] = acc[0];
 }
 
+// The previous launch's G partials of the four CG dots, summed in a fixed order (every block
+// gets bitwise the same totals); four partials per thread and dot are in flight at a time.
+template <int NT>
+__device__ __forceinline__ void sum_dot_partials(const double* __restrict__ part_in, int G,
+                                                 double (&v)[4]) {
+    for (int b0 = threadIdx.x; b0 < G; b0 += 4 * NT) {
+        double w[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u * NT;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) w[u][c] = b < G ? part_in[c * G + b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] += w[u][c];
+    }
+    block_sum_all<4, NT>(v);
+}
+
 // Dynamic LDS of k_cg_step, in doubles: sd [(T + hmax) N] directions d_k of the tile then of
 // its halo; sr [T N] residuals r_k of the tile; sm [T][3][N] per-lane partial rows.
 inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes) {
@@ -96,10 +117,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
     double alpha = 0.0, beta = 0.0;
     if (it > 0.0) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b = threadIdx.x; b < G; b += kBlockTri)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] += part_in[c * G + b];
-        block_sum_all<4, kBlockTri>(v);
+        sum_dot_partials<kBlockTri>(part_in, G, v);
         const double rr = v[0], dq = v[1], rq = v[2], qq = v[3];
         // every block takes the same decision from the same sums
         int stop = 0;
@@ -122,7 +140,16 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
     const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
     const Real ra = (Real)alpha, rb = (Real)beta;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t tile = blockIdx.x; tile * T < ne; tile += G) {
+    // This block's tiles: one contiguous chunk of the (Morton-ordered) tile range.  The
+    // dispatcher places block b on XCD b mod 8, so logical chunk (b mod 8) * G/8 + b/8 gives
+    // the blocks of one XCD a contiguous stretch of the mesh whose halos stay in that XCD's L2.
+    // G is a multiple of 8 (host side), so the map is a bijection onto the G chunks.
+    const int64_t ntiles = (ne + T - 1) / T;
+    const int lb = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+    const int64_t per = (ntiles + G - 1) / G;
+    const int64_t t_end = (lb + 1) * per < ntiles ? (lb + 1) * per : ntiles;
+    // loads per thread for the tile state and for one batch of halo entries
+    for (int64_t tile = lb * per; tile < t_end; ++tile) {
         const int64_t i0 = tile * T;
         const int nown = (int)((ne - i0) < T ? (ne - i0) : T) * N;
         const int64_t base = i0 * N;
@@ -185,137 +212,6 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
         __syncthreads();
     }
     block_sum_all<4, kBlockTri>(acc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) part_out[c * G + blockIdx.x] = acc[c];
-        if (blockIdx.x == 0) scal[S::ITER0 + (1 - parity)] = it + 1.0;
-    }
-}
-
-// Large meshes: one wave per tile, one lane per triangle (all three edges in the lane), so
-// waves of a CU progress independently (no block barrier inside the tile loop) and hide each
-// other's memory latency.  Per wave LDS: (T + hmax) N doubles of directions (tile, halo).
-constexpr int kWavesPerBlock = 4;
-constexpr int kBlockWave = 64 * kWavesPerBlock;
-
-inline size_t wave_lds_bytes(int nphi, int hmax) {
-    return sizeof(double) * (size_t)nphi * (size_t)(kTriPerBlock + hmax) * kWavesPerBlock;
-}
-
-template <int P>
-__global__ __launch_bounds__(kBlockWave) void k_cg_step_wave(
-    const RefOps<P>* __restrict__ ops, const double4* __restrict__ geo,
-    const int4* __restrict__ nbr, const int* __restrict__ halo_off,
-    const int* __restrict__ halo_ids, int hmax, int64_t ne, double* __restrict__ x,
-    const double* __restrict__ r_in, const double* __restrict__ q_in,
-    const double* __restrict__ d_in, double* __restrict__ r_out, double* __restrict__ q_out,
-    double* __restrict__ d_out, const double* __restrict__ part_in, double* __restrict__ part_out,
-    double* __restrict__ scal, int parity) {
-    constexpr int N = RefOps<P>::NPHI;
-    constexpr int T = kTriPerBlock;
-    static_assert(T == 64, "one lane per triangle of a tile");
-    extern __shared__ double lds[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double* sd = lds + (size_t)wave * (T + hmax) * N;
-    if (scal[S::DONE] != 0.0) return;
-    const int G = gridDim.x;
-    const double it = scal[S::ITER0 + parity];
-    double alpha = 0.0, beta = 0.0;
-    if (it > 0.0) {
-        double v[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b = threadIdx.x; b < G; b += kBlockWave)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] += part_in[c * G + b];
-        block_sum_all<4, kBlockWave>(v);
-        const double rr = v[0], dq = v[1], rq = v[2], qq = v[3];
-        int stop = 0;
-        if (!isfinite(rr)) stop = 3;
-        else if (rr <= scal[S::TOL2]) stop = 1;
-        else if (!(dq > 0.0) || !isfinite(dq)) stop = 3;
-        else if (it > scal[S::MAXIT]) stop = 2;
-        if (stop) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                scal[S::DONE] = (double)stop;
-                scal[S::RR] = rr;
-                scal[S::ITER] = it - 1.0;
-            }
-            return;
-        }
-        alpha = rr / dq;
-        const double rr_next = fma(alpha * alpha, qq, fma(-2.0 * alpha, rq, rr));
-        beta = rr_next / rr;
-    }
-    const RefOps<P>& R = *ops;
-    const int64_t ntiles = (ne + T - 1) / T;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave; tile < ntiles;
-         tile += (int64_t)G * kWavesPerBlock) {
-        const int64_t i = tile * T + lane;
-        const bool valid = i < ne;
-        double dk[N], rk[N];
-        if (valid) {
-#pragma unroll
-            for (int l = 0; l < N; ++l) {
-                const int64_t o = i * N + l;
-                const double dprev = d_in[o];
-                rk[l] = fma(-alpha, q_in[o], r_in[o]);
-                dk[l] = fma(beta, dprev, rk[l]);
-                x[o] = fma(alpha, dprev, x[o]);
-                r_out[o] = rk[l];
-                d_out[o] = dk[l];
-                sd[lane * N + l] = dk[l];
-                acc[0] = fma(rk[l], rk[l], acc[0]);
-            }
-        }
-        const int h0 = halo_off[tile];
-        const int nh = (halo_off[tile + 1] - h0) * N;
-        for (int e = lane; e < nh; e += 64) {
-            const int t = e / N;
-            const int64_t o = (int64_t)halo_ids[h0 + t] * N + (e - t * N);
-            sd[T * N + e] = fma(beta, d_in[o], fma(-alpha, q_in[o], r_in[o]));
-        }
-        wave_lds_fence();
-        if (valid) {
-            const double4 e = geo[i];
-            const Geo g = make_geo(e.x, e.y, e.z, e.w);
-            const double m00 = g.G00 * g.G00 + g.G01 * g.G01;
-            const double m01 = g.G00 * g.G10 + g.G01 * g.G11;
-            const double m11 = g.G10 * g.G10 + g.G11 * g.G11;
-            double y[N];
-            volume_term<P>(R, g.A, m00, m01, m11, dk, y);
-            const int4 nb4 = nbr[i];
-#pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                const int nb = al == 0 ? nb4.x : (al == 1 ? nb4.y : nb4.z);
-                const int slot = (nb4.w >> (10 * al)) & 1023;
-                double pr[N];
-                int ar = 0;
-                double4 er = make_double4(0, 0, 0, 0);
-                if (nb >= 0) {
-                    ar = nb & 3;
-#pragma unroll
-                    for (int l = 0; l < N; ++l) pr[l] = sd[slot * N + rot_sel<P>(ar, l)];
-                    er = geo[nb >> 2];
-                } else {
-#pragma unroll
-                    for (int l = 0; l < N; ++l) pr[l] = 0.0;
-                }
-                if (al == 0) edge_term<P, 0>(R, g, e, m00, m01, m11, nb, ar, er, dk, pr, y);
-                else if (al == 1) edge_term<P, 1>(R, g, e, m00, m01, m11, nb, ar, er, dk, pr, y);
-                else edge_term<P, 2>(R, g, e, m00, m01, m11, nb, ar, er, dk, pr, y);
-            }
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                const double qk = -y[k];
-                q_out[i * N + k] = qk;
-                acc[1] = fma(dk[k], qk, acc[1]);
-                acc[2] = fma(rk[k], qk, acc[2]);
-                acc[3] = fma(qk, qk, acc[3]);
-            }
-        }
-        wave_lds_fence();
-    }
-    block_sum_all<4, kBlockWave>(acc);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) part_out[c * G + blockIdx.x] = acc[c];
@@ -606,16 +502,7 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
     const CgWork& w = d->cg;
     const int G = w.grid;
     const int o = 1 - parity;
-    if (w.wave_kernel) {
-        const size_t lds = wave_lds_bytes(d->nphi, m->hmax);
-        SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_step_wave<PP>, dim3(G), dim3(kBlockWave), lds,
-                                              s, ops_of<PP>(d), m->geo_i, m->nbr_i, m->halo_off,
-                                              m->halo_ids, m->hmax, m->ne, w.x, w.r[parity],
-                                              w.q[parity], w.d[parity], w.r[o], w.q[o], w.d[o],
-                                              w.part + parity * 4 * G, w.part + o * 4 * G,
-                                              w.scal, parity));
-        return hipGetLastError();
-    }
+    if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double));
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>>), dim3(G), dim3(kBlockTri), lds, s,
                                           ops_of<PP>(d), m->geo_i, m->nbr_i, m->halo_off,
@@ -626,11 +513,22 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
     return hipGetLastError();
 }
 
-int cg_grid_for(int64_t ne, bool wave_kernel) {
-    const int64_t tiles = (ne + kTriPerBlock - 1) / kTriPerBlock;
-    if (!wave_kernel) return (int)(tiles < kCgMaxGrid ? tiles : kCgMaxGrid);
-    const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    return (int)(blocks < kCgMaxGridWave ? blocks : kCgMaxGridWave);
+// Grid of the CG iteration kernel: as many blocks as the device keeps resident at once (the
+// occupancy calculator, for this degree's kernel and LDS size), each owning a chunk of tiles,
+// or one block per tile on smaller meshes; a multiple of 8 for the per-XCD tile-chunk map.
+int cg_grid_for(const sld_disc_s* d) {
+    const sld_mesh_s* m = d->mesh;
+    const int64_t tiles = (m->ne + kTriPerBlock - 1) / kTriPerBlock;
+    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double));
+    int per_cu = 0, cus = 0;
+    hipError_t e = hipSuccess;
+    SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &per_cu, k_cg_step<PP, double, RefOps<PP>>, kBlockTri, lds));
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device);
+    int64_t resident = (e == hipSuccess && per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 1024;
+    int64_t g = tiles < resident ? tiles : resident;
+    if (g > kCgMaxGrid) g = kCgMaxGrid;
+    return (int)((g + 7) & ~int64_t(7));
 }
 
 hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s) {
@@ -656,6 +554,7 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
     const CgWork& w = d->cg;
     const int G = w.grid;
     const int o = 1 - parity;
+    if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float));
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>>), dim3(G),
                                           dim3(kBlockTri), lds, s, ops32_of<PP>(d), m->geo_i,
