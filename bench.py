@@ -54,6 +54,38 @@ def step_flops_per_tri(p: int) -> int:
     return 2 * fma
 
 
+KERNEL_SOURCES = ("kernels_cg.hip", "device_common.h", "refops.h", "sld_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2401_17806_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per CG-iteration launch from the committed byte-counter summary of this
+    workload (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading on a copy
+    kernel of known size), or None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"k_cg_step_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(wl, xy, tri, per, b_host, iters=200):
     """The oracle (assembled block-sparse K, plain CG) on the host: a bounded sample of
     `iters` CG iterations on the same system.  Assembly time reported separately."""
@@ -88,10 +120,6 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-12)
     ap.add_argument("--graph-block", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--timing", choices=("events", "graph"), default="events",
-                    help="events: every CG iteration launched directly and bracketed by HIP "
-                         "events on the solve stream (per-kernel durations); graph: captured "
-                         "graph blocks, per-iteration time from the solve's wall clock")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy MIB MiB device-to-device three times "
                          "(reference kernel for HBM byte counters)")
@@ -135,7 +163,7 @@ def main():
     reps = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        reps.append(step(profile=args.timing == "events"))
+        reps.append(step(profile=True))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -146,15 +174,14 @@ def main():
     div0 = disc.sld_divergence(vstar)
     divfree = float(torch.linalg.norm(div) / torch.linalg.norm(div0))
 
-    if args.timing == "events":
-        timed = sum(r["timed_iters"] for r in reps)
-        step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
-    else:
-        step_us = 1e6 * sum(r["seconds"] for r in reps) / max(iters, 1)
+    # per-iteration kernel time: HIP events on the solve stream around each captured block of
+    # graph_block iterations (the production path), blocks whose launches all iterated
+    timed = sum(r["timed_iters"] for r in reps)
+    step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
     sbytes = step_bytes_per_tri(nphi) * ne
     achieved = sbytes / (step_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                 "kernel": f"k_cg_step<{p}> (one fused CG iteration)",
                 "kernel_us": step_us, "bytes_per_launch": sbytes,
                 "fp64_tflops": step_flops_per_tri(p) * ne / (step_us * 1e-6) / 1e12,
@@ -187,11 +214,13 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl, xy, tri, per, b.cpu().numpy())
     print(json.dumps(out), flush=True)
     if args.copy_calibration > 0:
+        # an elementwise kernel that reads and writes nbytes each (a plain device copy may go
+        # to a DMA engine and leave no kernel dispatch to count)
         nbytes = args.copy_calibration << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print(f"copy calibration: 3 x {nbytes} bytes read and written", file=sys.stderr)
 

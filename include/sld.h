@@ -145,14 +145,16 @@ typedef struct {
     int32_t maxit;        /* iteration cap (mixed: per inner solve) */
     int32_t warm_start;   /* nonzero: p holds the initial guess */
     int32_t graph_block;  /* iterations per convergence check (even, 2..4096) */
-    int32_t profile;      /* nonzero: launch the iterations one by one (no graph) with a HIP
-                             event after each on `stream`; the report gives the mean time
-                             between consecutive iteration kernels (FP64 only) */
+    int32_t profile;      /* nonzero: HIP events on `stream` around each captured block of
+                             graph_block iterations; the report gives the mean time per
+                             iteration over the blocks whose launches all iterated (FP64 only) */
     int32_t precision;    /* 0: FP64 CG.  1: mixed: one CG process in FP32 (FP32 vectors and
                              operator arithmetic; FP64 geometry and dot products) refreshed by
                              FP64 reliable updates (x accumulated in FP64, residual b - K x
-                             recomputed in FP64, search direction kept).  Stops at rtol on the
-                             FP64 residual, or when it no longer improves (rounding floor) */
+                             recomputed in FP64; the search direction is kept while the
+                             recursive FP32 residual is within 0.3 of the recomputed one, else
+                             the FP32 process restarts).  Stops at rtol on the FP64 residual,
+                             or when it no longer improves (rounding floor) */
     int32_t max_outer;    /* mixed only: cap on reliable updates */
 } sld_cg_params;
 
@@ -162,7 +164,7 @@ typedef struct {
     double rel_res;       /* ||r|| / ||b|| at exit (FP64: recursive; mixed: FP64 residual) */
     double rel_res_true;  /* ||b - K p|| / ||b|| recomputed at exit */
     double seconds;       /* wall time of the solve on the host */
-    double step_us;       /* profile only: mean duration of one CG iteration kernel */
+    double step_us;       /* profile only: mean time per CG iteration inside captured blocks */
     int32_t timed_iters;  /* profile only: iterations the mean is taken over */
     int32_t outer_iters;  /* mixed only: reliable updates performed */
 } sld_cg_report;

@@ -764,26 +764,21 @@ sld_status run_iterations(sld_disc_s* d, bool fp32, int gb, bool prof, hipStream
     CgWork& w = d->cg;
     hipGraphExec_t& graph = fp32 ? w.graph32 : w.graph;
     int& graph_block = fp32 ? w.graph32_block : w.graph_block;
-    if (prof && (int)w.events.size() < gb + 1) {
+    if (prof && w.events.size() < 2) {
         for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
-        w.events.assign(gb + 1, nullptr);
+        w.events.assign(2, nullptr);
         for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
     }
-    if (!prof && (graph == nullptr || graph_block != gb)) {
+    if (graph == nullptr || graph_block != gb) {
         SLD_HIP_CHECK(capture_block(d, fp32, gb, &graph));
         graph_block = gb;
     }
     int launched = 0;
     while (true) {
-        if (prof) {
-            SLD_HIP_CHECK(hipEventRecord(w.events[0], s));
-            for (int k = 0; k < gb; ++k) {
-                SLD_HIP_CHECK(fp32 ? launch_cg_step32(d, k & 1, s) : launch_cg_step(d, k & 1, s));
-                SLD_HIP_CHECK(hipEventRecord(w.events[k + 1], s));
-            }
-        } else {
-            SLD_HIP_CHECK(hipGraphLaunch(graph, s));
-        }
+        // profile: HIP events on the solve stream around each captured block of gb launches
+        if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[0], s));
+        SLD_HIP_CHECK(hipGraphLaunch(graph, s));
+        if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[1], s));
         SLD_HIP_CHECK(hipMemcpyAsync(hs, scal, S::NSCAL * sizeof(double), hipMemcpyDeviceToHost, s));
         SLD_HIP_CHECK(hipStreamSynchronize(s));
         st->done = (int)hs[S::DONE];
@@ -791,14 +786,12 @@ sld_status run_iterations(sld_disc_s* d, bool fp32, int gb, bool prof, hipStream
         // launches that did work: the counter of the slot written last
         launched = (int)std::max(hs[S::ITER0], hs[S::ITER1]);
         st->iters = st->done ? (int)hs[S::ITER] : launched - 1;
-        if (prof) {
-            const int nk = launched - before;
-            for (int k = 0; k < nk && k < gb; ++k) {
-                float a = 0;
-                SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[k], w.events[k + 1]));
-                st->t_step += a;
-                ++st->timed;
-            }
+        if (prof && launched - before == gb) {
+            // only blocks whose launches all iterated (the last block of a solve exits early)
+            float a = 0;
+            SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[0], w.events[1]));
+            st->t_step += a;
+            st->timed += gb;
         }
         if (st->done) return SLD_OK;
     }
