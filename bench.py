@@ -37,10 +37,10 @@ FP64_PEAK_TFLOPS = 78.6
 A_SS = 0.43586652150845967
 
 
-def step_bytes_per_tri(nphi: int) -> int:
-    # one CG iteration kernel (k_cg_step): read x, r, q, d and write x, r, q, d (8 B per DOF
-    # each) plus the geometry (two edge vectors, 32 B) and the neighbour table (16 B)
-    return 8 * 8 * nphi + 48
+def step_bytes_per_tri(nphi: int, word: int = 8) -> int:
+    # one CG iteration kernel (k_cg_step): read x, r, q, d and write x, r, q, d (one word per
+    # DOF each) plus the geometry (two edge vectors, 32 B) and the neighbour table (16 B)
+    return 8 * word * nphi + 48
 
 
 def step_flops_per_tri(p: int) -> int:
@@ -117,7 +117,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument("--rtol", type=float, default=1e-12)
+    ap.add_argument("--rtol", type=float, default=None,
+                    help="CG tolerance (default 1e-12 FP64, 1e-11 mixed)")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="mixed: FP32 CG with FP64 reliable updates (true FP64 residual to rtol)")
     ap.add_argument("--graph-block", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -134,6 +137,9 @@ def main():
     from paper_2401_17806_amd import sld
     from paper_2401_17806_amd.inputs import lattice_mesh, random_fourier_field
 
+    if args.rtol is None:
+        args.rtol = 1e-12 if args.precision == "fp64" else 1e-11
+    mixed = args.precision == "mixed"
     wl = WORKLOADS[args.workload]
     n, p = wl["n"], wl["p"]
     xy, tri, per = lattice_mesh(n, seed=wl["seed"])
@@ -153,7 +159,8 @@ def main():
     def step(profile=False):
         disc.sld_pressure_rhs(vstar, 1.0 / coef, out=b)
         _, rep = disc.sld_cg_solve(b, p=pres, rtol=args.rtol, graph_block=args.graph_block,
-                                   profile=profile)
+                                   profile=profile and not mixed, precision=args.precision,
+                                   maxit=200000)
         disc.sld_velocity_correct(vstar, pres, coef, out=vnew)
         return rep
 
@@ -177,14 +184,23 @@ def main():
     # per-iteration kernel time: HIP events on the solve stream around each captured block of
     # graph_block iterations (the production path), blocks whose launches all iterated
     timed = sum(r["timed_iters"] for r in reps)
-    step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
-    sbytes = step_bytes_per_tri(nphi) * ne
+    if not mixed:
+        step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
+        sbytes = step_bytes_per_tri(nphi) * ne
+    else:
+        # FP32 inner iterations: solve wall time (refreshes included) per inner iteration
+        step_us = 1e6 * sum(r["seconds"] for r in reps) / max(iters, 1)
+        sbytes = step_bytes_per_tri(nphi, 4) * ne
     achieved = sbytes / (step_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
-                "kernel": f"k_cg_step<{p}> (one fused CG iteration)",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None if mixed else measured_traffic(args.workload),
+                "kernel": f"k_cg_step<{p}, {'float' if mixed else 'double'}> (one fused CG iteration)",
+                "kernel_us_source": ("solve wall time / inner iterations" if mixed else
+                                     "HIP events around captured blocks of iterations"),
                 "kernel_us": step_us, "bytes_per_launch": sbytes,
-                "fp64_tflops": step_flops_per_tri(p) * ne / (step_us * 1e-6) / 1e12,
+                ("fp32_tflops" if mixed else "fp64_tflops"):
+                    step_flops_per_tri(p) * ne / (step_us * 1e-6) / 1e12,
                 "fp64_peak_tflops": FP64_PEAK_TFLOPS}
 
     out = {
@@ -198,15 +214,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: periodic jittered {n}x{n}x2 = {ne} triangles, "
-                               f"p={p}, pressure stage (rhs + CG rtol {args.rtol:g} + correction)",
+                               f"p={p}, pressure stage (rhs + {args.precision} CG rtol {args.rtol:g} "
+                               f"+ correction)",
                    "triangles": ne, "p": p, "dofs": ne * nphi, "rtol": args.rtol},
         "cg_iters_per_step": iters / args.steps,
         "solve_ms_p50": float(np.percentile([r["seconds"] * 1e3 for r in reps], 50)),
         "solve_ms_p99": float(np.percentile([r["seconds"] * 1e3 for r in reps], 99)),
         "rel_res_true": max(r["rel_res_true"] for r in reps),
+        "precision": args.precision,
+        "outer_iters_per_step": sum(r["outer_iters"] for r in reps) / args.steps,
         "divergence_after_correction": divfree,
         "roofline": roofline,
     }

@@ -8,18 +8,18 @@
  * - Every function returns sld_status (SLD_OK = 0); none throws, aborts or exits.
  *   On failure sld_last_error() returns a thread-local message valid until the next
  *   call on the same thread.
- * - Degree p is 1..4.  N_phi = (p+1)(p+2)/2 main DOFs per triangle (Section 2.2),
- *   N_psi = (p+1)^2 dual DOFs per edge (Section 2.2).
+ * - Degree p is 1..4.  N_phi = (p+1)(p+2)/2 main DOFs per triangle (Section 3.2),
+ *   N_psi = (p+1)^2 dual DOFs per edge (Section 3.2).
  * - Main (pressure) vectors: float64 [ne][N_phi], row-major, triangle-major.  DOF k of
  *   a triangle is the Lagrange node (a/p, b/p) of the reference triangle, numbered with
  *   b outer and a inner, mapped by the affine map of eq. linmap (vertex 0 -> (0,0),
  *   vertex 1 -> (1,0), vertex 2 -> (0,1)).
  * - Dual (velocity) vectors: float64 [nd][2][N_psi]: edge-major, then component x/y,
  *   then dual node (a/p, b/p) of the reference square numbered k = b*(p+1) + a
- *   (Section 2.2).  Nodes with a+b <= p lie in the left sub-triangle (b_l, A, B) with
+ *   (Section 3.2).  Nodes with a+b <= p lie in the left sub-triangle (b_l, A, B) with
  *   (1,0) -> A, (0,1) -> B; nodes with a+b > p lie in the right sub-triangle through
  *   x = b_r + (1-b/p)(A-b_r) + (1-a/p)(B-b_r) (eq. mapDual).
- * - Edge numbering (Section 2.1 leaves l and r arbitrary): edges are numbered in order of
+ * - Edge numbering (Section 3.1 leaves l and r arbitrary): edges are numbered in order of
  *   first appearance scanning triangles i = 0.. and local edges alpha = 0,1,2, i.e. the
  *   vertex pairs (v0,v1), (v1,v2), (v2,v0).  l(j) is the first triangle that references
  *   edge j, A -> B follow l's counter-clockwise order, the unit normal n_j points from l
@@ -59,10 +59,10 @@ const char* sld_last_error(void);
 /* ABI version of this header (bumped on incompatible changes). */
 int32_t sld_abi_version(void);
 
-/* ------------------------------------------------------------------ mesh (Section 2.1)
+/* ------------------------------------------------------------------ mesh (Section 3.1)
  * sld_mesh_create: build the staggered mesh from host arrays.
  *   xy     host float64 [nv][2] vertex coordinates
- *   tri    host int32 [ne][3] vertex ids, counter-clockwise (positive Jacobian, Section 2.4.1)
+ *   tri    host int32 [ne][3] vertex ids, counter-clockwise (positive Jacobian, Section 3.4.1)
  *   period host float64 [2] periodic box lengths, or NULL for a bounded domain.  For a
  *          periodic box every triangle is unwrapped to the image of each vertex nearest
  *          to its vertex 0, so triangles must be smaller than half a period.
@@ -73,7 +73,7 @@ int32_t sld_abi_version(void);
  * triangles with opposite orientation, no edge joining a triangle to itself
  * (SLD_E_MESH otherwise).  Stores per triangle only its two edge vectors and its
  * neighbour table on the device (the paper's point that only geometric quantities are
- * stored per element, Section 2.4.1). */
+ * stored per element, Section 3.4.1). */
 sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int64_t ne,
                            const double* period, int32_t device, sld_mesh* out);
 sld_status sld_mesh_counts(sld_mesh mesh, int64_t* ne, int64_t* nd, int64_t* nv);
@@ -86,7 +86,7 @@ sld_status sld_mesh_edges(sld_mesh mesh, int32_t* left, int32_t* right,
 void sld_mesh_destroy(sld_mesh mesh);
 
 /* ------------------------------------------------------------------ discretisation
- * sld_disc_create: reference operators of degree p (Section 2.4: mass matrices and the
+ * sld_disc_create: reference operators of degree p (Section 3.4: mass matrices and the
  * reference divergence/gradient operators, here in the equivalent form of reference
  * stiffness, edge-node derivative and sub-triangle correction matrices), computed on the
  * host in float64 by exact Gauss quadrature, plus the solver workspace on the device.
@@ -126,7 +126,7 @@ sld_status sld_pressure_rhs(sld_disc disc, const double* v_star, double scale, d
 sld_status sld_velocity_correct(sld_disc disc, const double* v_star, const double* p,
                                 double coef, double* v, void* stream);
 
-/* ------------------------------------------------------------------ CG (Section 2.3)
+/* ------------------------------------------------------------------ CG (Section 3.3)
  * sld_cg_solve: matrix-free conjugate gradients for K p = b (run on -K, which is SPSD).
  *   b device [ne][N_phi]; it is projected onto the complement of the constant vector
  *   (the kernel of K on a periodic or all-wall mesh) before the solve.

@@ -11,15 +11,15 @@ What the oracle computes is the plain definition of the method's objects
 IMEX discontinuous Galerkin methods on staggered unstructured meshes"):
 
 * main nodal basis on T_ref and the C0 dual basis on the split reference
-  square (Section 2.2);
+  square (Section 3.2);
 * per-edge dual mass matrix (eq. Mj), gradient operator (eq. ad5.2) and
   divergence operator (eq. D), each integrated in PHYSICAL space by Gauss
   quadrature over the sub-triangles T_{l(j),j}, T_{r(j),j} and the edge
-  Gamma_j (Section 2.3), not through the reference factorisation of
-  Section 2.4;
+  Gamma_j (Section 3.3), not through the reference factorisation of
+  Section 3.4;
 * the pressure Schur operator K = sum_j D_ij Mhat_j^-1 (Q_lj p_l + Q_rj p_r)
   of eq. pressure_final, assembled block-sparse, and its solution by plain
-  conjugate gradients (Section 2.3) or, on tiny meshes, a dense bordered
+  conjugate gradients (Section 3.3) or, on tiny meshes, a dense bordered
   direct solve.
 
 Readings where the paper is silent or garbled are documented where used

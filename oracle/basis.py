@@ -1,12 +1,12 @@
-"""Main and dual nodal bases (Section 2.2).
+"""Main and dual nodal bases (Section 3.2).
 
-Main basis (Section 2.2, "simple nodal approach"): Lagrange polynomials of
+Main basis (Section 3.2, "simple nodal approach"): Lagrange polynomials of
 total degree p on T_ref = {xi >= 0, eta >= 0, xi + eta <= 1}, N_phi =
 (p+1)(p+2)/2.  Reading of the unspecified node set: the equispaced lattice
 (a/p, b/p), a + b <= p, numbered with b outer and a inner.  The polynomials
 are obtained by inverting the monomial Vandermonde matrix at the nodes.
 
-Dual basis (Section 2.2, the p = 1 example and the split of R_ref into two
+Dual basis (Section 3.2, the p = 1 example and the split of R_ref into two
 sub-triangles): nodes (a/p, b/p), a, b = 0..p on R_ref = [0,1]^2, numbered
 k = b*(p+1) + a, N_psi = (p+1)^2.  On the lower sub-triangle xi + eta <= 1
 psi_k equals the main basis function of node (a, b) (zero when the node lies
@@ -96,7 +96,7 @@ def grad_phi(p: int, xi, eta) -> np.ndarray:
 
 
 def psi(p: int, xi, eta) -> np.ndarray:
-    """Dual basis values on R_ref, shape [..., N_psi] (definition of Section 2.2)."""
+    """Dual basis values on R_ref, shape [..., N_psi] (definition of Section 3.2)."""
     xi = np.asarray(xi, dtype=np.float64)
     eta = np.asarray(eta, dtype=np.float64)
     idx = main_index(p)

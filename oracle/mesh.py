@@ -1,4 +1,4 @@
-"""Staggered mesh bookkeeping (Section 2.1).
+"""Staggered mesh bookkeeping (Section 3.1).
 
 From vertex coordinates and counter-clockwise triangles the oracle builds,
 with its own loops:
@@ -17,7 +17,7 @@ with its own loops:
 * the periodic shift s_j: r's copy of the edge equals l's copy plus s_j.
 
 A boundary edge (walls) has r(j) = -1; its dual cell is the left
-sub-triangle only (Section 2.1).
+sub-triangle only (Section 3.1).
 """
 from __future__ import annotations
 

@@ -19,7 +19,7 @@ the image of the upper half with (1,0) -> A, (0,1) -> B, (1,1) -> b_r.  The
 diagonal of R_ref is therefore Gamma_j traversed from A to B, as seen from
 both sides, which is what makes the C0 dual space single valued on Gamma_j.
 
-Nothing here uses the reference-operator factorisation of Section 2.4.
+Nothing here uses the reference-operator factorisation of Section 3.4.
 """
 from __future__ import annotations
 

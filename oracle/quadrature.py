@@ -1,7 +1,7 @@
 """Gauss quadrature on [0, 1] and on triangles.
 
 The paper integrates with "Gauss quadrature" without naming a rule
-(Section 2.5, eq. intstage).  The oracle only needs rules that are exact for
+(Section 4, eq. intstage).  The oracle only needs rules that are exact for
 the polynomial integrands of the operator definitions (degree <= 2p), so any
 exact rule gives the same operators to rounding.
 

@@ -1,4 +1,4 @@
-"""Pressure Schur system and its solution (Section 2.3, eq. pressure_final).
+"""Pressure Schur system and its solution (Section 3.3, eq. pressure_final).
 
 K p |_i = sum_{j in S_i} D_ij Mhat_j^{-1} (Q_{l(j),j} p_l + Q_{r(j),j} p_r)
 
@@ -7,10 +7,10 @@ assembled as a block-sparse matrix from the physical-quadrature blocks of
 over interior edges only (reading: wall dual cells hold prescribed velocity
 and enter the right-hand side only).
 
-Sign reading: with D = -Q^T (Section 2.3, after eq. ad5) K is symmetric
+Sign reading: with D = -Q^T (Section 3.3, after eq. ad5) K is symmetric
 NEGATIVE semi-definite, a discrete Laplacian; the paper calls the pressure
 system "symmetric and semi-positive definite", which holds for -K.  Plain
-conjugate gradients (Section 2.3) are therefore run on -K p = -b.
+conjugate gradients (Section 3.3) are therefore run on -K p = -b.
 
 Null space and gauge readings: on a periodic (or all-wall) connected mesh
 K 1 = 0 for the nodal coefficient vector 1, and 1^T D v = 0.  The right-hand

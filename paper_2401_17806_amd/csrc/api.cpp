@@ -1,5 +1,5 @@
-// C ABI entry points: argument checking, host-side mesh setup (Section 2.1), reference
-// operators (Section 2.4), device buffers and the CG driver (Section 2.3).
+// C ABI entry points: argument checking, host-side mesh setup (Section 3.1), reference
+// operators (Section 3.4), device buffers and the CG driver (Section 3.3).
 #include <algorithm>
 #include <chrono>
 #include <cmath>

@@ -1,7 +1,7 @@
 // Device helpers shared by the operator and CG kernels (gfx950, wave64).
 //
 // Operator form used on the device (equivalent to eq. pressure_final, derived from the
-// reference factorisation of Section 2.4 and the split dual space of Section 2.2):
+// reference factorisation of Section 3.4 and the split dual space of Section 3.2):
 //
 // For triangle i with affine map x = P0 + J xi (eq. linmap), A_i = det J = 2|T_i|,
 // G = J^{-1}, and an edge alpha shared with triangle r:
@@ -12,12 +12,12 @@
 //     with g_s = grad p_s at the edge nodes, delta = p_r - p_i at the edge nodes (jump term
 //     of eq. ad5.2, C = S0^{-1} M1), and inside each half ghat = grad p_s + sum_m Delta_m chi_m
 //     with Delta = x_H - g_s;
-//   * the divergence D = -Q^T (Section 2.3) tested with phi_k then gives
+//   * the divergence D = -Q^T (Section 3.3) tested with phi_k then gives
 //       (K p)_i = -A_i sum_{de} (G G^T)_{de} S_{de} p_i
 //                 + sum_alpha [ |Gamma| M1 (n . x_H) on the edge nodes
 //                               - A_i sum_d Pt_alpha,d (G Delta)_d ].
 // Everything per element is the two edge vectors of the triangle (32 bytes) and its
-// neighbour table: no per-element operator is stored (Section 2.4.1).
+// neighbour table: no per-element operator is stored (Section 3.4.1).
 //
 // Work split: three lanes per triangle, lane alpha owning local edge alpha.  Each lane works
 // in the triangle's frame relabelled so that its edge is local edge 0 (a cyclic renaming of

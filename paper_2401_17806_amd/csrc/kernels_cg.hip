@@ -1,4 +1,4 @@
-// Matrix-free conjugate gradients on -K (Section 2.3: the pressure system of eq.
+// Matrix-free conjugate gradients on -K (Section 3.3: the pressure system of eq.
 // pressure_final is symmetric, so CG applies; K itself is negative semi-definite).
 //
 // One iteration = ONE kernel on a fixed grid of G blocks (k_cg_step).  Launch k reads the
@@ -11,7 +11,7 @@
 //   r_k = r_{k-1} - alpha q_{k-1},  d_k = r_k + beta d_{k-1},  x += alpha d_{k-1}
 //   q_k = -K d_k   (neighbours' r_k, d_k are recomputed from their (r, q, d)_{k-1})
 //   partials of rr_k = r_k.r_k, dq_k = d_k.q_k, rq_k = r_k.q_k, qq_k = q_k.q_k.
-// In exact arithmetic this is plain CG (Section 2.3).  Global scalars are never published
+// In exact arithmetic this is plain CG (Section 3.3).  Global scalars are never published
 // through in-kernel atomics: every block sums the previous launch's partials itself in a
 // fixed order, so all blocks take bitwise identical decisions and results are deterministic.
 // The iteration counter is double-buffered by parity for the same reason.

@@ -1,4 +1,4 @@
-// Host construction of the reference operators (Section 2.4) for degree P.
+// Host construction of the reference operators (Section 3.4) for degree P.
 //
 // Basis: equispaced Lagrange polynomials on T_ref written in product form over the
 // integer barycentric coordinates (a, b, c = P-a-b) of their node,

@@ -1,4 +1,4 @@
-// Reference operators of degree P on the reference triangle (Section 2.4), in the
+// Reference operators of degree P on the reference triangle (Section 3.4), in the
 // triangle-centred form the kernels use.  Filled on the host in float64 by exact Gauss
 // quadrature (refops.cpp), copied once to the device.
 //

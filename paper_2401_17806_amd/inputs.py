@@ -6,7 +6,7 @@ operators).  Both sides receive the arrays it returns.
 
 Meshes follow the experiments' setting of a square box covered by n x n
 squares, each split on its diagonal into two counter-clockwise triangles
-(Section 4, Taylor-Green vortex on [0, 2*pi]^2 with periodic boundaries).
+(Section 5, Taylor-Green vortex on [0, 2*pi]^2 with periodic boundaries).
 Vertices strictly inside the box are jittered i.i.d. uniformly in
 [-jitter*h, +jitter*h] per coordinate; vertices on the box boundary stay on
 the lattice so that periodic images are exact shifts.

@@ -1,0 +1,135 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py times
+(default grid, graph blocks of 64 iterations).  The oracle cannot assemble or solve these
+systems quickly, so outputs are checked on samples it computes one by one:
+  * the Schur apply on 256 sampled triangles (rows of eq. pressure_final, oracle.schur_rows);
+  * the 128x128x2, p = 3 pressure against the oracle's own solve at 512 sampled DOFs
+    (tests/golden/c2_pressure_sample.txt, written by make_c2_sample.py from the oracle);
+  * on the 512x512x2 mesh, properties that hold at any size: the true residual on sampled
+    rows and the zero-mean gauge; the mixed form's pressure against the FP64 one.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import solve
+from oracle.mesh import OracleMesh
+from oracle.operators import OracleDisc
+from paper_2401_17806_amd.inputs import lattice_mesh, random_fourier_field, random_vector
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+A_SS = 0.43586652150845967
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+_CACHE = {}
+
+
+def _setup(n, p, seed):
+    key = (n, p, seed)
+    if key not in _CACHE:
+        from paper_2401_17806_amd import sld
+        xy, tri, per = lattice_mesh(n, seed=seed)
+        od = OracleDisc(OracleMesh(xy, tri, per), p)
+        mesh = sld.Mesh(xy, tri, per, device=0)
+        _CACHE[key] = (od, mesh, sld.Disc(mesh, p))
+    return _CACHE[key]
+
+
+def _rhs(torch, od, disc, n, rhs_seed):
+    """The bench right-hand side: (1/(a_ss dt)) D v*, v* a seeded Fourier field."""
+    coef = A_SS * 0.5 * (2 * math.pi / n)
+    vs = random_fourier_field(rhs_seed, kmax=8)(od.dual_node_xy()).transpose(0, 2, 1)
+    vt = torch.from_numpy(np.ascontiguousarray(vs)).to("cuda:0")
+    return disc.sld_pressure_rhs(vt, 1.0 / coef)
+
+
+@pytest.mark.parametrize("n,p,seed", [(128, 3, 2), (512, 3, 3), (256, 4, 1005)])
+def test_fullsize_schur_apply_sampled_rows(torch_dev, n, p, seed):
+    torch = torch_dev
+    _say(f"[fullsize apply] n={n} p={p}")
+    od, mesh, disc = _setup(n, p, seed)
+    x = random_vector((mesh.ne, disc.nphi), seed=500 + n)
+    got = disc.sld_schur_apply(torch.from_numpy(x).to("cuda:0")).cpu().numpy()
+    ids = np.sort(np.random.default_rng(n).choice(mesh.ne, 256, replace=False))
+    want = solve.schur_rows(od, x, ids)
+    rel = np.linalg.norm(got[ids] - want) / np.linalg.norm(want)
+    _say(f"    sampled rel L2 {rel:.2e}")
+    assert rel <= 1e-12
+
+
+def _read_sample():
+    idx, val, head = [], [], {}
+    for line in open(os.path.join(HERE, "golden", "c2_pressure_sample.txt")):
+        if line.startswith("#"):
+            parts = line[1:].split()
+            for k in range(0, len(parts) - 1):
+                if parts[k] in ("maxabs_p", "norm2_p", "rel_res_true"):
+                    head[parts[k]] = float(parts[k + 1])
+            continue
+        i, v = line.split()
+        idx.append(int(i))
+        val.append(float(v))
+    return np.array(idx), np.array(val), head
+
+
+def test_fullsize_c2_pressure_matches_oracle_sample(torch_dev):
+    """Bench workload (128x128x2, p = 3, FP64, rtol 1e-12, graph blocks of 64): the pressure
+    at 512 sampled DOFs equals the oracle's to 1e-9 of its max norm."""
+    torch = torch_dev
+    _say("[fullsize c2 solve]")
+    od, mesh, disc = _setup(128, 3, 2)
+    b = _rhs(torch, od, disc, 128, 102)
+    p_gpu, rep = disc.sld_cg_solve(b, rtol=1e-12, graph_block=64, maxit=100000)
+    _say("   report", rep)
+    idx, val, head = _read_sample()
+    got = p_gpu.cpu().numpy().ravel()[idx]
+    err = np.abs(got - val).max() / head["maxabs_p"]
+    _say(f"    sampled max error / max|p| = {err:.2e}")
+    assert rep["converged"]
+    assert err <= 1e-9
+
+
+def test_fullsize_c3_solution_properties(torch_dev):
+    """512x512x2, p = 3: FP64 solve in the bench configuration; the true residual on 256
+    sampled rows is at the FP64 floor, the gauge holds, and the mixed form's pressure agrees
+    with the FP64 one."""
+    torch = torch_dev
+    _say("[fullsize c3 solve]")
+    od, mesh, disc = _setup(512, 3, 3)
+    b = _rhs(torch, od, disc, 512, 103)
+    p64, rep = disc.sld_cg_solve(b, rtol=1e-12, graph_block=64, maxit=200000)
+    _say("   fp64 report", rep)
+    assert rep["converged"]
+    bh = b.cpu().numpy()
+    bh = bh - bh.mean()
+    ph = p64.cpu().numpy()
+    ids = np.sort(np.random.default_rng(5).choice(mesh.ne, 256, replace=False))
+    res = bh[ids] - solve.schur_rows(od, ph, ids)
+    rel = np.linalg.norm(res) / np.linalg.norm(bh[ids])
+    _say(f"    sampled true residual {rel:.2e} (reported full {rep['rel_res_true']:.2e})")
+    assert rel <= 1e-7
+    w = od.main_weights()
+    assert abs((w * ph).sum()) <= 1e-12 * np.abs(ph).max() * w.sum()
+    pm, repm = disc.sld_cg_solve(b, rtol=1e-11, precision="mixed", graph_block=64, maxit=200000)
+    _say("   mixed report", repm)
+    d = np.linalg.norm(pm.cpu().numpy() - ph) / np.linalg.norm(ph)
+    _say(f"    mixed vs fp64 rel L2 {d:.2e}")
+    assert repm["rel_res_true"] <= 1e-10
+    assert d <= 1e-9

@@ -48,7 +48,7 @@ def test_gauss_legendre_exact(n):
         assert abs((w * t ** k).sum() - 1.0 / (k + 1)) < 1e-14
 
 
-# ---------------------------------------------------------------- basis (Section 2.2)
+# ---------------------------------------------------------------- basis (Section 3.2)
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_main_basis_lagrange_unity(p):
     nd = basis.main_nodes(p)
@@ -80,7 +80,7 @@ def test_dual_basis_lagrange_unity_c0(p):
 
 
 def test_dual_basis_p1_worked_example():
-    """The p = 1 example of Section 2.2, written out in tests/golden/dual_basis_p1.txt."""
+    """The p = 1 example of Section 3.2, written out in tests/golden/dual_basis_p1.txt."""
     rows = _read_rows("dual_basis_p1.txt")
     rng = np.random.default_rng(2)
     x, y = rng.random(200), rng.random(200)
@@ -95,7 +95,7 @@ def test_dual_basis_p1_worked_example():
         assert np.abs(ps[mask, k] - ref[mask]).max() < 1e-14
 
 
-# ---------------------------------------------------------------- mass matrices (Section 2.4.1)
+# ---------------------------------------------------------------- mass matrices (Section 3.4.1)
 def _single(tri_xy):
     return OracleMesh(np.asarray(tri_xy, float), np.array([[0, 1, 2]]), None)
 
@@ -135,10 +135,10 @@ def test_dual_mass_invariants(p):
     assert np.isfinite(bmin).all()
 
 
-# ---------------------------------------------------------------- operators (Section 2.3)
+# ---------------------------------------------------------------- operators (Section 3.3)
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_divergence_is_minus_gradient_transpose(p):
-    """D = -Q^T (Section 2.3 after eq. ad5), from two separate integrations."""
+    """D = -Q^T (Section 3.3 after eq. ad5), from two separate integrations."""
     xy, tri, per = lattice_mesh(4, seed=5)
     m = OracleMesh(xy, tri, per)
     blk = OracleDisc(m, p).edge_blocks(np.arange(m.nd))
@@ -222,7 +222,7 @@ def test_divergence_of_polynomial_field(p):
 @pytest.mark.parametrize("n", [3, 4])
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_cg_matches_dense_bordered_solve(n, p):
-    """Plain CG (Section 2.3) against a dense direct solve of the bordered system."""
+    """Plain CG (Section 3.3) against a dense direct solve of the bordered system."""
     xy, tri, per = lattice_mesh(n, seed=13)
     d = OracleDisc(OracleMesh(xy, tri, per), p)
     K = solve.assemble_K(d)
@@ -338,3 +338,17 @@ def test_planted_jump_sign_error_is_caught(monkeypatch):
     integral = np.einsum("ekl,eck->ec", Mh, g)
     want = (c[m.right] - c[m.left])[:, None] * m.edge_len[:, None] * (-m.normal)
     assert np.abs(integral - want).max() > 1e-3
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_schur_rows_equal_assembled_rows(periodic):
+    """Sampled rows of K p, computed edge by edge without assembly (used at full size), equal
+    the rows of the assembled K (itself pinned above)."""
+    xy, tri, per = lattice_mesh(5, seed=9, periodic=periodic, length=(2 * np.pi if periodic else 1.0))
+    d = OracleDisc(OracleMesh(xy, tri, per), 2)
+    K = solve.assemble_K(d)
+    x = np.random.default_rng(3).standard_normal((d.mesh.ne, d.nphi))
+    ids = np.array([0, 7, 13, 21, d.mesh.ne - 1])
+    want = (K @ x.ravel()).reshape(d.mesh.ne, d.nphi)[ids]
+    got = solve.schur_rows(d, x, ids)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
