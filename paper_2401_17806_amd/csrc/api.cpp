@@ -74,8 +74,7 @@ void free_mesh(sld_mesh_s* m) {
     dfree(m->nbr);
     dfree(m->edges);
     dfree(m->tedges);
-    dfree(m->halo_off);
-    dfree(m->halo_ids);
+    dfree(m->halo_pad);
     dfree(m->perm);
     dfree(m->geo_i);
     dfree(m->nbr_i);
@@ -441,6 +440,13 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
             halo_off[t + 1] = (int)halo_ids.size();
         }
         m->halo_total = (int64_t)halo_ids.size();
+        // fixed-stride copy of the halo lists (hmax entries per tile, -1 padded) so that a
+        // tile's halo ids are addressable without first reading its offset
+        const int hstride = std::max(m->hmax, 1);
+        std::vector<int> halo_pad(size_t(ntiles) * hstride, -1);
+        for (int64_t t = 0; t < ntiles; ++t)
+            for (int k = halo_off[t]; k < halo_off[t + 1]; ++k)
+                halo_pad[size_t(t) * hstride + (k - halo_off[t])] = halo_ids[k];
         if (device == -1) {
             *out = m;  // host-only handle: tables and node queries, no device work
             return SLD_OK;
@@ -461,14 +467,12 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
         if (e == hipSuccess) e = dalloc(&m->perm, ne);
         if (e == hipSuccess) e = dalloc(&m->geo_i, ne);
         if (e == hipSuccess) e = dalloc(&m->nbr_i, ne);
-        if (e == hipSuccess) e = dalloc(&m->halo_off, halo_off.size());
-        if (e == hipSuccess) e = dalloc(&m->halo_ids, halo_ids.size());
+        if (e == hipSuccess) e = dalloc(&m->halo_pad, halo_pad.size());
         if (e == hipSuccess) {
             up.copy(m->perm, perm.data(), sizeof(int) * ne);
             up.copy(m->geo_i, geo_i.data(), sizeof(double4) * ne);
             up.copy(m->nbr_i, nbr_i.data(), sizeof(int4) * ne);
-            up.copy(m->halo_off, halo_off.data(), sizeof(int) * halo_off.size());
-            up.copy(m->halo_ids, halo_ids.data(), sizeof(int) * halo_ids.size());
+            up.copy(m->halo_pad, halo_pad.data(), sizeof(int) * halo_pad.size());
             up.copy(m->geo, geo.data(), sizeof(double4) * ne);
             up.copy(m->nbr, nbr.data(), sizeof(int4) * ne);
             up.copy(m->tedges, tedges.data(), sizeof(int4) * ne);

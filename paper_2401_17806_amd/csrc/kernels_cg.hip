@@ -89,12 +89,15 @@ inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes) {
                                                 3 * kTriPerBlock);
 }
 
-template <int P, typename Real, class Ops>
+// kFront: the grid has one tile per block (cache-resident meshes, latency-bound).  Every load
+// that does not depend on alpha and beta -- the tile's state, its halo ids, the previous
+// launch's dot partials and the scalars -- is issued at entry, so their latencies overlap;
+// otherwise (several tiles per block) the loads follow the tile loop.
+template <int P, typename Real, class Ops, bool kFront>
 __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ ops,
                                                        const double4* __restrict__ geo,
                                                        const int4* __restrict__ nbr,
-                                                       const int* __restrict__ halo_off,
-                                                       const int* __restrict__ halo_ids, int hmax,
+                                                       const int* __restrict__ halo_pad, int hmax,
                                                        int64_t ne, Real* __restrict__ x,
                                                        const Real* __restrict__ r_in,
                                                        const Real* __restrict__ q_in,
@@ -107,18 +110,65 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
                                                        double* __restrict__ scal, int parity) {
     constexpr int N = RefOps<P>::NPHI;
     constexpr int T = kTriPerBlock;
+    constexpr int PER = (T * N + kBlockTri - 1) / kBlockTri;  // tile entries per thread
+    constexpr int HB = 4;                                     // halo entries per thread and batch
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Real* sd = reinterpret_cast<Real*>(lds_raw);
     Real* sr = sd + (size_t)(T + hmax) * N;
     Real* sm = sr + (size_t)T * N;
-    if (scal[S::DONE] != 0.0) return;
     const int G = gridDim.x;
+    const int hs = hmax > 0 ? hmax : 1;  // row stride of halo_pad
+    const int nhe = hmax * N;            // halo entries (padded) of a tile
+    // This block's tiles: one contiguous chunk of the (Morton-ordered) tile range.  The
+    // dispatcher places block b on XCD b mod 8, so logical chunk (b mod 8) * G/8 + b/8 gives
+    // the blocks of one XCD a contiguous stretch of the mesh whose halos stay in that XCD's L2.
+    // G is a multiple of 8 (host side), so the map is a bijection onto the G chunks.
+    const int64_t ntiles = (ne + T - 1) / T;
+    const int lb = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+    const int64_t per = (ntiles + G - 1) / G;
+    const int64_t t_begin = lb * per;
+    const int64_t t_end = (lb + 1) * per < ntiles ? (lb + 1) * per : ntiles;
+
+    Real vd[PER], vq[PER], vr[PER], vx[PER];
+    int hid[HB];
+    // state of tile `tile` into registers
+    auto load_own = [&](int64_t tile) {
+        const int64_t i0 = tile * T;
+        const int nown = (int)((ne - i0) < T ? (ne - i0) : T) * N;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int f = threadIdx.x + u * kBlockTri;
+            if (f < nown) {
+                const int64_t o = i0 * N + f;
+                vd[u] = d_in[o];
+                vq[u] = q_in[o];
+                vr[u] = r_in[o];
+                vx[u] = x[o];
+            }
+        }
+    };
+    // halo triangle ids of one batch of halo entries (-1: padding)
+    auto load_hid = [&](int64_t tile, int e0) {
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+            const int e = e0 + threadIdx.x + u * kBlockTri;
+            hid[u] = e < nhe ? halo_pad[tile * hs + e / N] : -1;
+        }
+    };
+    if constexpr (kFront) {
+        if (t_begin < t_end) {
+            load_own(t_begin);
+            load_hid(t_begin, 0);
+        }
+    }
+    const double done = scal[S::DONE];
     const double it = scal[S::ITER0 + parity];
     double alpha = 0.0, beta = 0.0;
     if (it > 0.0) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         sum_dot_partials<kBlockTri>(part_in, G, v);
         const double rr = v[0], dq = v[1], rq = v[2], qq = v[3];
+        if (done != 0.0) return;
         // every block takes the same decision from the same sums
         int stop = 0;
         if (!isfinite(rr)) stop = 3;
@@ -136,42 +186,76 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
         alpha = rr / dq;
         const double rr_next = fma(alpha * alpha, qq, fma(-2.0 * alpha, rq, rr));
         beta = rr_next / rr;
+    } else if (done != 0.0) {
+        return;
     }
     const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
     const Real ra = (Real)alpha, rb = (Real)beta;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    // This block's tiles: one contiguous chunk of the (Morton-ordered) tile range.  The
-    // dispatcher places block b on XCD b mod 8, so logical chunk (b mod 8) * G/8 + b/8 gives
-    // the blocks of one XCD a contiguous stretch of the mesh whose halos stay in that XCD's L2.
-    // G is a multiple of 8 (host side), so the map is a bijection onto the G chunks.
-    const int64_t ntiles = (ne + T - 1) / T;
-    const int lb = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
-    const int64_t per = (ntiles + G - 1) / G;
-    const int64_t t_end = (lb + 1) * per < ntiles ? (lb + 1) * per : ntiles;
-    // loads per thread for the tile state and for one batch of halo entries
-    for (int64_t tile = lb * per; tile < t_end; ++tile) {
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
         const int64_t i0 = tile * T;
         const int nown = (int)((ne - i0) < T ? (ne - i0) : T) * N;
         const int64_t base = i0 * N;
         // phase 1: state update of the tile (coalesced) and directions of tile + halo into LDS
-        for (int f = threadIdx.x; f < nown; f += kBlockTri) {
-            const int64_t o = base + f;
-            const Real dprev = d_in[o];
-            const Real rk = mad(-ra, q_in[o], r_in[o]);
-            const Real dk = mad(rb, dprev, rk);
-            x[o] = mad(ra, dprev, x[o]);
-            r_out[o] = rk;
-            d_out[o] = dk;
-            sd[f] = dk;
-            sr[f] = rk;
-            acc[0] = fma((double)rk, (double)rk, acc[0]);
-        }
-        const int h0 = halo_off[tile];
-        const int nh = (halo_off[tile + 1] - h0) * N;
-        for (int e = threadIdx.x; e < nh; e += kBlockTri) {
-            const int t = e / N;
-            const int64_t o = (int64_t)halo_ids[h0 + t] * N + (e - t * N);
-            sd[T * N + e] = mad(rb, d_in[o], mad(-ra, q_in[o], r_in[o]));
+        if constexpr (kFront) {
+            // the loads were issued at entry
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int f = threadIdx.x + u * kBlockTri;
+                if (f < nown) {
+                    const int64_t o = base + f;
+                    const Real rk = mad(-ra, vq[u], vr[u]);
+                    const Real dk = mad(rb, vd[u], rk);
+                    x[o] = mad(ra, vd[u], vx[u]);
+                    r_out[o] = rk;
+                    d_out[o] = dk;
+                    sd[f] = dk;
+                    sr[f] = rk;
+                    acc[0] = fma((double)rk, (double)rk, acc[0]);
+                }
+            }
+            for (int e0 = 0; e0 < nhe; e0 += HB * kBlockTri) {
+                if (e0 > 0) load_hid(tile, e0);
+                Real hd[HB], hq[HB], hr[HB];
+#pragma unroll
+                for (int u = 0; u < HB; ++u) {
+                    if (hid[u] >= 0) {
+                        const int e = e0 + threadIdx.x + u * kBlockTri;
+                        const int64_t o = (int64_t)hid[u] * N + (e - (e / N) * N);
+                        hd[u] = d_in[o];
+                        hq[u] = q_in[o];
+                        hr[u] = r_in[o];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < HB; ++u) {
+                    if (hid[u] >= 0) {
+                        const int e = e0 + threadIdx.x + u * kBlockTri;
+                        sd[T * N + e] = mad(rb, hd[u], mad(-ra, hq[u], hr[u]));
+                    }
+                }
+            }
+        } else {
+            // several tiles per block: plain loops (fewer live registers, higher occupancy)
+            for (int f = threadIdx.x; f < nown; f += kBlockTri) {
+                const int64_t o = base + f;
+                const Real dprev = d_in[o];
+                const Real rk = mad(-ra, q_in[o], r_in[o]);
+                const Real dk = mad(rb, dprev, rk);
+                x[o] = mad(ra, dprev, x[o]);
+                r_out[o] = rk;
+                d_out[o] = dk;
+                sd[f] = dk;
+                sr[f] = rk;
+                acc[0] = fma((double)rk, (double)rk, acc[0]);
+            }
+            for (int e = threadIdx.x; e < nhe; e += kBlockTri) {
+                const int id = halo_pad[tile * hs + e / N];
+                if (id >= 0) {
+                    const int64_t o = (int64_t)id * N + (e - (e / N) * N);
+                    sd[T * N + e] = mad(rb, d_in[o], mad(-ra, q_in[o], r_in[o]));
+                }
+            }
         }
         __syncthreads();
         // phase 2: three lanes per triangle, operands from LDS
@@ -504,12 +588,20 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
     const int o = 1 - parity;
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double));
-    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>>), dim3(G), dim3(kBlockTri), lds, s,
-                                          ops_of<PP>(d), m->geo_i, m->nbr_i, m->halo_off,
-                                          m->halo_ids, m->hmax, m->ne, w.x, w.r[parity], w.q[parity],
-                                          w.d[parity], w.r[o], w.q[o], w.d[o],
-                                          w.part + parity * 4 * G, w.part + o * 4 * G, w.scal,
-                                          parity));
+    const bool front = (int64_t)G * kTriPerBlock >= m->ne;  // one tile per block
+#define SLD_STEP64(F)                                                                           \
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F>), dim3(G),      \
+                                          dim3(kBlockTri), lds, s, ops_of<PP>(d), m->geo_i,     \
+                                          m->nbr_i, m->halo_pad, m->hmax, m->ne, w.x,           \
+                                          w.r[parity], w.q[parity], w.d[parity], w.r[o],        \
+                                          w.q[o], w.d[o], w.part + parity * 4 * G,              \
+                                          w.part + o * 4 * G, w.scal, parity))
+    if (front) {
+        SLD_STEP64(true);
+    } else {
+        SLD_STEP64(false);
+    }
+#undef SLD_STEP64
     return hipGetLastError();
 }
 
@@ -523,7 +615,7 @@ int cg_grid_for(const sld_disc_s* d) {
     int per_cu = 0, cus = 0;
     hipError_t e = hipSuccess;
     SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &per_cu, k_cg_step<PP, double, RefOps<PP>>, kBlockTri, lds));
+                           &per_cu, (k_cg_step<PP, double, RefOps<PP>, false>), kBlockTri, lds));
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device);
     int64_t resident = (e == hipSuccess && per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 1024;
     int64_t g = tiles < resident ? tiles : resident;
@@ -556,12 +648,21 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
     const int o = 1 - parity;
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float));
-    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>>), dim3(G),
-                                          dim3(kBlockTri), lds, s, ops32_of<PP>(d), m->geo_i,
-                                          m->nbr_i, m->halo_off, m->halo_ids, m->hmax, m->ne, w.e32,
-                                          w.r32[parity], w.q32[parity], w.d32[parity], w.r32[o],
-                                          w.q32[o], w.d32[o], w.part32 + parity * 4 * G,
-                                          w.part32 + o * 4 * G, w.scal_in, parity));
+    const bool front = (int64_t)G * kTriPerBlock >= m->ne;  // one tile per block
+#define SLD_STEP32(F)                                                                           \
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>, F>), dim3(G),     \
+                                          dim3(kBlockTri), lds, s, ops32_of<PP>(d), m->geo_i,   \
+                                          m->nbr_i, m->halo_pad, m->hmax, m->ne, w.e32,         \
+                                          w.r32[parity], w.q32[parity], w.d32[parity],          \
+                                          w.r32[o], w.q32[o], w.d32[o],                         \
+                                          w.part32 + parity * 4 * G, w.part32 + o * 4 * G,      \
+                                          w.scal_in, parity))
+    if (front) {
+        SLD_STEP32(true);
+    } else {
+        SLD_STEP32(false);
+    }
+#undef SLD_STEP32
     return hipGetLastError();
 }
 

@@ -50,8 +50,8 @@ struct sld_mesh_s {
     double4* geo_i = nullptr;      // [ne] geo in internal order
     int4* nbr_i = nullptr;         // [ne] internal neighbour ids (packed as nbr); w = the three
                                    // tile-local slots (10 bits each): 0..63 own tile, 64+h halo
-    int* halo_off = nullptr;       // [ntiles + 1] offsets into halo_ids
-    int* halo_ids = nullptr;       // halo triangles (internal ids) of every tile, sorted
+    int* halo_pad = nullptr;       // [ntiles][max(hmax, 1)] halo triangles (internal ids) of
+                                   // every tile, sorted, -1 padded
     int hmax = 0;                  // largest halo
     int64_t halo_total = 0;        // sum of halo sizes (diagnostics)
     int4* edges = nullptr;         // [nd] (l, r, alpha_l, alpha_r)

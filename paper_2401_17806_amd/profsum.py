@@ -6,9 +6,10 @@
       mean per dispatch of every counter of a --pmc run, over the matching dispatches
   python -m paper_2401_17806_amd.profsum traffic FETCH_DB WRITE_DB --workload W --bytes B
       HBM bytes per CG-iteration launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of
-      k_cg_step, each divided by the same counter's reading per byte on the calibration copy
-      kernel (an elementwise kernel that reads and writes a known number of bytes); B is the
-      copy size in bytes.  Prints the markdown lines bench.py reads back.
+      k_cg_step, each divided by the same counter's reading per byte on the calibration kernel
+      (bench.py --copy-calibration: torch's elementwise multiply by a scalar, whose kernel name
+      carries AUnaryFunctor, reading and writing B bytes).  Prints the markdown lines bench.py
+      reads back.
 """
 from __future__ import annotations
 
@@ -68,8 +69,8 @@ def traffic(fetch_db: str, write_db: str, workload: str, copy_bytes: int) -> Non
             h.update(f.read())
     f_cg = counter_means(fetch_db, "k_cg_step")
     w_cg = counter_means(write_db, "k_cg_step")
-    f_cp = counter_means(fetch_db, "elementwise")
-    w_cp = counter_means(write_db, "elementwise")
+    f_cp = counter_means(fetch_db, "AUnaryFunctor")
+    w_cp = counter_means(write_db, "AUnaryFunctor")
     ff = f_cp["FETCH_SIZE"] * 1024.0 / copy_bytes
     wf = w_cp["WRITE_SIZE"] * 1024.0 / copy_bytes
     hbm = f_cg["FETCH_SIZE"] * 1024.0 / ff + w_cg["WRITE_SIZE"] * 1024.0 / wf
