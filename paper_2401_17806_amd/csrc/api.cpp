@@ -542,7 +542,9 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     DeviceGuard dg(m->device);
     const size_t nv = size_t(m->ne) * d->nphi;
     CgWork& w = d->cg;
-    int G = cg_grid_for(d);
+    bool front = false;
+    int G = cg_grid_for(d, &front);
+    w.front = front;
     if (const char* gcap = std::getenv("SLD_CG_GRID")) {  // debugging aid: grid size cap
         const int cap = std::atoi(gcap);
         if (cap > 0 && cap < G) G = (cap + 7) & ~7;

@@ -34,6 +34,7 @@ namespace sld_dev {
 
 constexpr int kBlockTri = 3 * kTriPerBlock;      // 192 threads: three lanes per triangle
 constexpr int kBlockFlat = 256;                  // threads of flat (per-DOF) kernels
+constexpr int kBlockCG = 4 * kTriPerBlock;       // 256 threads: CG iteration, one wave per role
 
 template <int P>
 struct Tab {
@@ -231,6 +232,123 @@ __device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, 
         for (int m = 0; m < NE; ++m) {
             s = mad(R.Pt[0][0][k][m], gd0[m], s);
             s = mad(R.Pt[0][1][k][m], gd1[m], s);
+        }
+        y[k] = mad(-g.A, s, y[k]);
+    }
+}
+
+// Natural-frame forms used by the CG iteration kernel, one wave per role: waves 0..2 take
+// local edge AL of every triangle of a tile (one lane per triangle), wave 3 the volume term.
+// pl = p_i in its own (natural) numbering; pr = the neighbour's DOFs relabelled by ar (its shared
+// edge is its local edge 0); e / er are the two triangles' edge vectors (v1 - v0, v2 - v0).
+// The result y holds this role's contribution to the rows of (K p)_i (natural numbering).
+
+// Volume term -A (m00 S0 + m01 S1 + m11 S2) p over all rows.
+template <int P, class Ops, typename Real>
+__device__ __forceinline__ void volume_wave_core(const Ops& R, double4 e,
+                                                 const Real (&pl)[RefOps<P>::NPHI],
+                                                 Real (&y)[RefOps<P>::NPHI]) {
+    constexpr int N = RefOps<P>::NPHI;
+    const Geo gd = make_geo(e.x, e.y, e.z, e.w);
+    const Real A = (Real)gd.A;
+    const Real m00 = (Real)(gd.G00 * gd.G00 + gd.G01 * gd.G01);
+    const Real m01 = (Real)(gd.G00 * gd.G10 + gd.G01 * gd.G11);
+    const Real m11 = (Real)(gd.G10 * gd.G10 + gd.G11 * gd.G11);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        Real s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            s0 = mad(R.S[0][k][l], pl[l], s0);
+            s1 = mad(R.S[1][k][l], pl[l], s1);
+            s2 = mad(R.S[2][k][l], pl[l], s2);
+        }
+        y[k] = -A * (m00 * s0 + m01 * s1 + m11 * s2);
+    }
+}
+
+// Edge AL (compile time) of triangle i: the dual coupling through that edge (edge-node
+// gradients of both sides, jump, projected gradient x_H, line term and sub-triangle
+// correction), or on a wall edge the sub-triangle share of the volume term given back.
+template <int P, int AL, class Ops, typename Real>
+__device__ __forceinline__ void edge_wave_core(const Ops& R, double4 e, int nb, int ar, double4 er,
+                                               const Real (&pl)[RefOps<P>::NPHI],
+                                               const Real (&pr)[RefOps<P>::NPHI],
+                                               Real (&y)[RefOps<P>::NPHI]) {
+    constexpr int N = RefOps<P>::NPHI;
+    constexpr int NE = P + 1;
+    const Geo gd = make_geo(e.x, e.y, e.z, e.w);
+    const GeoR<Real> g(gd);
+#pragma unroll
+    for (int k = 0; k < N; ++k) y[k] = Real(0);
+    if (nb < 0) {
+        const Real m00 = (Real)(gd.G00 * gd.G00 + gd.G01 * gd.G01);
+        const Real m01 = (Real)(gd.G00 * gd.G10 + gd.G01 * gd.G11);
+        const Real m11 = (Real)(gd.G10 * gd.G10 + gd.G11 * gd.G11);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            Real s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                s0 = mad(R.Sh[AL][0][k][l], pl[l], s0);
+                s1 = mad(R.Sh[AL][1][k][l], pl[l], s1);
+                s2 = mad(R.Sh[AL][2][k][l], pl[l], s2);
+            }
+            y[k] = g.A * (m00 * s0 + m01 * s1 + m11 * s2);
+        }
+        return;
+    }
+    // |Gamma| n, outward: the edge vector v_{AL+1} - v_AL turned clockwise
+    const double ex = AL == 0 ? e.x : (AL == 1 ? e.z - e.x : -e.z);
+    const double ey = AL == 0 ? e.y : (AL == 1 ? e.w - e.y : -e.w);
+    const Real snx = (Real)ey, sny = (Real)(-ex);
+    double f1x, f1y, f2x, f2y;
+    relabel(er, ar, f1x, f1y, f2x, f2y);
+    const Geo grd = make_geo(f1x, f1y, f2x, f2y);
+    const GeoR<Real> gr(grd);
+    const Real wsum = (Real)(1.0 / (gd.A + grd.A));
+    Real delta[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) delta[m] = pr[P - m] - pl[edge_node(P, AL, m)];
+    Real gd0[NE], gd1[NE], tn[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        Real ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            ds0 = mad(R.E[AL][0][m][l], pl[l], ds0);
+            ds1 = mad(R.E[AL][1][m][l], pl[l], ds1);
+            dn0 = mad(R.E[0][0][P - m][l], pr[l], dn0);
+            dn1 = mad(R.E[0][1][P - m][l], pr[l], dn1);
+        }
+        const Real gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
+        const Real gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
+        Real cd = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) cd = mad(R.C[m][q], delta[q], cd);
+        const Real hx = (g.A * gsx + gr.A * gnx + Real(3) * snx * cd) * wsum;
+        const Real hy = (g.A * gsy + gr.A * gny + Real(3) * sny * cd) * wsum;
+        tn[m] = snx * hx + sny * hy;
+        const Real dx = hx - gsx, dy = hy - gsy;
+        gd0[m] = g.G00 * dx + g.G01 * dy;
+        gd1[m] = g.G10 * dx + g.G11 * dy;
+    }
+    // line term |Gamma| int phi_k n.x_H on the edge nodes
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        Real s = 0;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) s = mad(R.M1[m][q], tn[q], s);
+        y[edge_node(P, AL, m)] = s;
+    }
+    // sub-triangle correction -A sum_d Pt_d (G Delta)_d
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        Real s = 0;
+#pragma unroll
+        for (int m = 0; m < NE; ++m) {
+            s = mad(R.Pt[AL][0][k][m], gd0[m], s);
+            s = mad(R.Pt[AL][1][k][m], gd1[m], s);
         }
         y[k] = mad(-g.A, s, y[k]);
     }

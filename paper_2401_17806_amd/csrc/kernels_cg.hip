@@ -82,11 +82,12 @@ __device__ __forceinline__ void sum_dot_partials(const double* __restrict__ part
     block_sum_all<4, NT>(v);
 }
 
-// Dynamic LDS of k_cg_step, in doubles: sd [(T + hmax) N] directions d_k of the tile then of
-// its halo; sr [T N] residuals r_k of the tile; sm [T][3][N] per-lane partial rows.
-inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes) {
-    return real_bytes * (size_t)nphi * (size_t)(kTriPerBlock + hmax + kTriPerBlock +
-                                                3 * kTriPerBlock);
+// Dynamic LDS of k_cg_step, in words of the arithmetic type: sd [(T + hmax) N] directions d_k
+// of the tile then of its halo; sr [T N] residuals r_k of the tile; sm [T][R][N] partial rows
+// (R = 4 roles in the one-tile-per-block variant, 3 lanes otherwise).
+inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes, bool front) {
+    return real_bytes * (size_t)nphi *
+           (size_t)(kTriPerBlock + hmax + kTriPerBlock + (front ? 4 : 3) * kTriPerBlock);
 }
 
 // kFront: the grid has one tile per block (cache-resident meshes, latency-bound).  Every load
@@ -94,7 +95,7 @@ inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes) {
 // launch's dot partials and the scalars -- is issued at entry, so their latencies overlap;
 // otherwise (several tiles per block) the loads follow the tile loop.
 template <int P, typename Real, class Ops, bool kFront>
-__global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ ops,
+__global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const Ops* __restrict__ ops,
                                                        const double4* __restrict__ geo,
                                                        const int4* __restrict__ nbr,
                                                        const int* __restrict__ halo_pad, int hmax,
@@ -110,7 +111,9 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
                                                        double* __restrict__ scal, int parity) {
     constexpr int N = RefOps<P>::NPHI;
     constexpr int T = kTriPerBlock;
-    constexpr int PER = (T * N + kBlockTri - 1) / kBlockTri;  // tile entries per thread
+    constexpr int NT = kFront ? kBlockCG : kBlockTri;  // threads
+    constexpr int R = kFront ? 4 : 3;                  // partial rows per triangle
+    constexpr int PER = (T * N + NT - 1) / NT;  // tile entries per thread
     constexpr int HB = 4;                                     // halo entries per thread and batch
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Real* sd = reinterpret_cast<Real*>(lds_raw);
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
         const int nown = (int)((ne - i0) < T ? (ne - i0) : T) * N;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const int f = threadIdx.x + u * kBlockTri;
+            const int f = threadIdx.x + u * NT;
             if (f < nown) {
                 const int64_t o = i0 * N + f;
                 vd[u] = d_in[o];
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
     auto load_hid = [&](int64_t tile, int e0) {
 #pragma unroll
         for (int u = 0; u < HB; ++u) {
-            const int e = e0 + threadIdx.x + u * kBlockTri;
+            const int e = e0 + threadIdx.x + u * NT;
             hid[u] = e < nhe ? halo_pad[tile * hs + e / N] : -1;
         }
     };
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
     double alpha = 0.0, beta = 0.0;
     if (it > 0.0) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
-        sum_dot_partials<kBlockTri>(part_in, G, v);
+        sum_dot_partials<NT>(part_in, G, v);
         const double rr = v[0], dq = v[1], rq = v[2], qq = v[3];
         if (done != 0.0) return;
         // every block takes the same decision from the same sums
@@ -189,7 +192,6 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
     } else if (done != 0.0) {
         return;
     }
-    const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
     const Real ra = (Real)alpha, rb = (Real)beta;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t tile = t_begin; tile < t_end; ++tile) {
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
             // the loads were issued at entry
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
-                const int f = threadIdx.x + u * kBlockTri;
+                const int f = threadIdx.x + u * NT;
                 if (f < nown) {
                     const int64_t o = base + f;
                     const Real rk = mad(-ra, vq[u], vr[u]);
@@ -214,13 +216,13 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
                     acc[0] = fma((double)rk, (double)rk, acc[0]);
                 }
             }
-            for (int e0 = 0; e0 < nhe; e0 += HB * kBlockTri) {
+            for (int e0 = 0; e0 < nhe; e0 += HB * NT) {
                 if (e0 > 0) load_hid(tile, e0);
                 Real hd[HB], hq[HB], hr[HB];
 #pragma unroll
                 for (int u = 0; u < HB; ++u) {
                     if (hid[u] >= 0) {
-                        const int e = e0 + threadIdx.x + u * kBlockTri;
+                        const int e = e0 + threadIdx.x + u * NT;
                         const int64_t o = (int64_t)hid[u] * N + (e - (e / N) * N);
                         hd[u] = d_in[o];
                         hq[u] = q_in[o];
@@ -230,14 +232,14 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
 #pragma unroll
                 for (int u = 0; u < HB; ++u) {
                     if (hid[u] >= 0) {
-                        const int e = e0 + threadIdx.x + u * kBlockTri;
+                        const int e = e0 + threadIdx.x + u * NT;
                         sd[T * N + e] = mad(rb, hd[u], mad(-ra, hq[u], hr[u]));
                     }
                 }
             }
         } else {
             // several tiles per block: plain loops (fewer live registers, higher occupancy)
-            for (int f = threadIdx.x; f < nown; f += kBlockTri) {
+            for (int f = threadIdx.x; f < nown; f += NT) {
                 const int64_t o = base + f;
                 const Real dprev = d_in[o];
                 const Real rk = mad(-ra, q_in[o], r_in[o]);
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
                 sr[f] = rk;
                 acc[0] = fma((double)rk, (double)rk, acc[0]);
             }
-            for (int e = threadIdx.x; e < nhe; e += kBlockTri) {
+            for (int e = threadIdx.x; e < nhe; e += NT) {
                 const int id = halo_pad[tile * hs + e / N];
                 if (id >= 0) {
                     const int64_t o = (int64_t)id * N + (e - (e / N) * N);
@@ -258,35 +260,78 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
             }
         }
         __syncthreads();
-        // phase 2: three lanes per triangle, operands from LDS
-        const int64_t i = i0 + tl;
-        if (i < ne) {
-            const int4 nb4 = nbr[i];
-            const int nb = pick(nb4, al);
-            const int slot = (nb4.w >> (10 * al)) & 1023;
-            Real pl[N], pr[N], y[N];
+        if constexpr (kFront) {
+            // phase 2: one wave per role (waves 0..2: local edge 0..2, wave 3: volume term), one
+            // lane per triangle, operands from LDS.  Four waves per tile keep the SIMDs of a
+            // CU evenly loaded when the grid is a single tile per block.
+            const int role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            const int lane = threadIdx.x & 63;
+            const int64_t i = i0 + lane;
+            if (i < ne) {
+                Real pl[N], y[N];
 #pragma unroll
-            for (int l = 0; l < N; ++l) pl[l] = sd[tl * N + rot_sel<P>(al, l)];
-            int ar = 0;
-            double4 er = make_double4(0, 0, 0, 0);
-            if (nb >= 0) {
-                ar = nb & 3;
+                for (int l = 0; l < N; ++l) pl[l] = sd[lane * N + l];
+                const double4 e = geo[i];
+                if (role == 3) {
+                    volume_wave_core<P, Ops, Real>(*ops, e, pl, y);
+                } else {
+                    const int4 nb4 = nbr[i];
+                    const int nb = pick(nb4, role);
+                    const int slot = (nb4.w >> (10 * role)) & 1023;
+                    Real pr[N];
+                    int ar = 0;
+                    double4 er = make_double4(0, 0, 0, 0);
+                    if (nb >= 0) {
+                        ar = nb & 3;
 #pragma unroll
-                for (int l = 0; l < N; ++l) pr[l] = sd[slot * N + rot_sel<P>(ar, l)];
-                er = geo[nb >> 2];
-            } else {
+                        for (int l = 0; l < N; ++l) pr[l] = sd[slot * N + rot_sel<P>(ar, l)];
+                        er = geo[nb >> 2];
+                    } else {
 #pragma unroll
-                for (int l = 0; l < N; ++l) pr[l] = Real(0);
+                        for (int l = 0; l < N; ++l) pr[l] = Real(0);
+                    }
+                    if (role == 0) edge_wave_core<P, 0, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y);
+                    else if (role == 1) edge_wave_core<P, 1, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y);
+                    else edge_wave_core<P, 2, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y);
+                }
+#pragma unroll
+                for (int k = 0; k < N; ++k) sm[(lane * 4 + role) * N + k] = y[k];
             }
-            edge_lane_core<P, Ops, Real>(al, *ops, geo[i], nb, ar, er, pl, pr, y);
+        } else {
+            // phase 2: three lanes per triangle (lane al owns local edge al, in the frame
+            // relabelled so that it is edge 0), operands from LDS
+            const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
+            const int64_t i = i0 + tl;
+            if (i < ne) {
+                const int4 nb4 = nbr[i];
+                const int nb = pick(nb4, al);
+                const int slot = (nb4.w >> (10 * al)) & 1023;
+                Real pl[N], pr[N], y[N];
 #pragma unroll
-            for (int k = 0; k < N; ++k) sm[(tl * 3 + al) * N + rot_sel<P>(al, k)] = y[k];
+                for (int l = 0; l < N; ++l) pl[l] = sd[tl * N + rot_sel<P>(al, l)];
+                int ar = 0;
+                double4 er = make_double4(0, 0, 0, 0);
+                if (nb >= 0) {
+                    ar = nb & 3;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) pr[l] = sd[slot * N + rot_sel<P>(ar, l)];
+                    er = geo[nb >> 2];
+                } else {
+#pragma unroll
+                    for (int l = 0; l < N; ++l) pr[l] = Real(0);
+                }
+                edge_lane_core<P, Ops, Real>(al, *ops, geo[i], nb, ar, er, pl, pr, y);
+#pragma unroll
+                for (int k = 0; k < N; ++k) sm[(tl * 3 + al) * N + rot_sel<P>(al, k)] = y[k];
+            }
         }
         __syncthreads();
         // phase 3: q_k = -K d_k (coalesced) and the dot products
-        for (int f = threadIdx.x; f < nown; f += kBlockTri) {
+        for (int f = threadIdx.x; f < nown; f += NT) {
             const int t = f / N, k = f - t * N;
-            const Real qk = -(sm[(t * 3) * N + k] + sm[(t * 3 + 1) * N + k] + sm[(t * 3 + 2) * N + k]);
+            Real qk = (sm[(t * R) * N + k] + sm[(t * R + 1) * N + k]) + sm[(t * R + 2) * N + k];
+            if constexpr (R == 4) qk += sm[(t * R + 3) * N + k];
+            qk = -qk;
             q_out[base + f] = qk;
             const double dk = sd[f], rk = sr[f], qd = qk;
             acc[1] = fma(dk, qd, acc[1]);
@@ -295,7 +340,7 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_step(const Ops* __restrict__ o
         }
         __syncthreads();
     }
-    block_sum_all<4, kBlockTri>(acc);
+    block_sum_all<4, NT>(acc);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) part_out[c * G + blockIdx.x] = acc[c];
@@ -587,11 +632,12 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
     const int G = w.grid;
     const int o = 1 - parity;
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
-    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double));
-    const bool front = (int64_t)G * kTriPerBlock >= m->ne;  // one tile per block
+    const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
+    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double), front);
 #define SLD_STEP64(F)                                                                           \
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F>), dim3(G),      \
-                                          dim3(kBlockTri), lds, s, ops_of<PP>(d), m->geo_i,     \
+                                          dim3(F ? kBlockCG : kBlockTri), lds, s, ops_of<PP>(d), \
+                                          m->geo_i,                                             \
                                           m->nbr_i, m->halo_pad, m->hmax, m->ne, w.x,           \
                                           w.r[parity], w.q[parity], w.d[parity], w.r[o],        \
                                           w.q[o], w.d[o], w.part + parity * 4 * G,              \
@@ -605,21 +651,36 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Grid of the CG iteration kernel: as many blocks as the device keeps resident at once (the
-// occupancy calculator, for this degree's kernel and LDS size), each owning a chunk of tiles,
-// or one block per tile on smaller meshes; a multiple of 8 for the per-XCD tile-chunk map.
-int cg_grid_for(const sld_disc_s* d) {
+// Grid of the CG iteration kernel.  Meshes whose tiles all fit on the device at once run the
+// one-tile-per-block (front-loaded, four-role) variant; larger meshes run as many blocks as the
+// device keeps resident (occupancy calculator, for this degree's kernel and LDS size), each
+// owning a chunk of tiles.  The grid is a multiple of 8 for the per-XCD tile-chunk map.
+int cg_grid_for(const sld_disc_s* d, bool* front) {
     const sld_mesh_s* m = d->mesh;
     const int64_t tiles = (m->ne + kTriPerBlock - 1) / kTriPerBlock;
-    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double));
-    int per_cu = 0, cus = 0;
+    int per_front = 0, per_lanes = 0, cus = 0;
     hipError_t e = hipSuccess;
+    const size_t lds_f = step_lds_bytes(d->nphi, m->hmax, sizeof(double), true);
+    const size_t lds_l = step_lds_bytes(d->nphi, m->hmax, sizeof(double), false);
     SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &per_cu, (k_cg_step<PP, double, RefOps<PP>, false>), kBlockTri, lds));
+                           &per_front, (k_cg_step<PP, double, RefOps<PP>, true>), kBlockCG, lds_f));
+    if (e == hipSuccess)
+        SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                               &per_lanes, (k_cg_step<PP, double, RefOps<PP>, false>), kBlockTri,
+                               lds_l));
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device);
-    int64_t resident = (e == hipSuccess && per_cu > 0 && cus > 0) ? (int64_t)per_cu * cus : 1024;
-    int64_t g = tiles < resident ? tiles : resident;
-    if (g > kCgMaxGrid) g = kCgMaxGrid;
+    const bool ok = e == hipSuccess && cus > 0;
+    const int64_t res_front = ok ? (int64_t)per_front * cus : 0;
+    const int64_t res_lanes = ok && per_lanes > 0 ? (int64_t)per_lanes * cus : 1024;
+    int64_t g;
+    if (tiles <= res_front) {
+        *front = true;
+        g = tiles;
+    } else {
+        *front = false;
+        g = tiles < res_lanes ? tiles : res_lanes;
+        if (g > kCgMaxGrid) g = kCgMaxGrid;
+    }
     return (int)((g + 7) & ~int64_t(7));
 }
 
@@ -647,11 +708,12 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
     const int G = w.grid;
     const int o = 1 - parity;
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
-    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float));
-    const bool front = (int64_t)G * kTriPerBlock >= m->ne;  // one tile per block
+    const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
+    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float), front);
 #define SLD_STEP32(F)                                                                           \
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>, F>), dim3(G),     \
-                                          dim3(kBlockTri), lds, s, ops32_of<PP>(d), m->geo_i,   \
+                                          dim3(F ? kBlockCG : kBlockTri), lds, s, ops32_of<PP>(d), \
+                                          m->geo_i,                                             \
                                           m->nbr_i, m->halo_pad, m->hmax, m->ne, w.e32,         \
                                           w.r32[parity], w.q32[parity], w.d32[parity],          \
                                           w.r32[o], w.q32[o], w.d32[o],                         \

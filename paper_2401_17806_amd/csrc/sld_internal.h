@@ -72,6 +72,7 @@ struct CgWork {
     double* scal = nullptr;        // device scalars (CgScalars)
     double* host_scal = nullptr;   // pinned mirror of scal
     int grid = 0;                  // blocks of every CG kernel
+    bool front = false;            // iteration kernel variant: one tile per block, four roles
     std::vector<hipEvent_t> events;  // profiling events (created on first profiled solve)
     // mixed precision: FP32 inner CG state (e32 = the correction), its partials and scalars
     float* r32[2] = {nullptr, nullptr};
@@ -114,7 +115,7 @@ struct CgScalars {
     enum { RR = 0, BB = 1, TOL2 = 2, ITER = 3, DONE = 4, MAXIT = 5, MEAN = 6, ZERO = 7,
            RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, IRS = 12, RRNOW = 13, GAP = 14, NSCAL = 16 };
 };
-int cg_grid_for(const sld_disc_s* d);
+int cg_grid_for(const sld_disc_s* d, bool* front);
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
                            double rtol, int maxit, hipStream_t s);
 hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s);
