@@ -126,6 +126,24 @@ sld_status sld_pressure_rhs(sld_disc disc, const double* v_star, double scale, d
 sld_status sld_velocity_correct(sld_disc disc, const double* v_star, const double* p,
                                 double coef, double* v, void* stream);
 
+/* ------------------------------------------------------------------ semi-Lagrangian stage
+ * sld_sl_advect: advection of main-grid DG fields over one step dt (Section 3.5; the Gauss-point
+ * projection of the SL-IMEX stages, eq. intstage).  For every triangle and every point of the
+ * collapsed Gauss-Legendre rule with p + 1 points per direction, the backward characteristic
+ * is followed cell by cell with straight (explicit Euler) segments, the velocity of each
+ * segment being the current cell's DG velocity at the segment's start; crossing an interior
+ * edge continues in the neighbour (periodic boxes included), a wall edge or a cell whose
+ * velocity points straight back out ends the walk.  The fields are evaluated at the foot in
+ * the cell reached and projected onto the main basis:
+ *   q_out_i = M_ref^{-1} sum_g w_g phi(xi_g) q(foot_g).
+ *   vbar   device float64 [ne][2][N_phi]: nodal DG velocity on the main grid
+ *   q      device float64 [ne][nc][N_phi]: the nc fields to advect (1 <= nc <= 8)
+ *   dt     the time step (the trace goes back by dt)
+ *   q_out  device float64 [ne][nc][N_phi]; must not alias q or vbar
+ * Asynchronous on `stream`.  SLD_E_INVALID for bad arguments. */
+sld_status sld_sl_advect(sld_disc disc, const double* vbar, const double* q, int32_t nc, double dt,
+                         double* q_out, void* stream);
+
 /* ------------------------------------------------------------------ CG (Section 3.3)
  * sld_cg_solve: matrix-free conjugate gradients for K p = b (run on -K, which is SPSD).
  *   b device [ne][N_phi]; it is projected onto the complement of the constant vector

@@ -117,3 +117,22 @@ def nodal_velocity(disc: OracleDisc, field) -> np.ndarray:
     """Nodal DG velocity [ne, 2, N] of a callable field(x [..., 2]) -> [..., 2] at the main nodes."""
     xy = disc.main_node_xy()  # [ne, N, 2]
     return np.ascontiguousarray(field(xy).transpose(0, 2, 1))
+
+
+def sl_advect_rows(disc: OracleDisc, vbar: np.ndarray, q: np.ndarray, dt: float, tri_ids,
+                   max_steps: int = 1024) -> np.ndarray:
+    """The advected coefficients of the triangles in tri_ids only, [len(tri_ids), nc, N]
+    (the same computation as sl_advect, for checks on large meshes)."""
+    p = disc.p
+    pts, _ = sl_rule(p)
+    proj = projection_matrix(p)
+    nc = q.shape[1]
+    out = np.zeros((len(tri_ids), nc, disc.nphi))
+    for t, i in enumerate(tri_ids):
+        qf = np.zeros((pts.shape[0], nc))
+        for g in range(pts.shape[0]):
+            c, (a, b), _ = walk(disc, vbar, int(i), pts[g], dt, max_steps)
+            ph = basis.phi(p, np.array([a]), np.array([b]))[0]
+            qf[g] = q[c] @ ph
+        out[t] = (proj @ qf).T
+    return out

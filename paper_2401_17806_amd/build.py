@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsld.so")
 
-SOURCES = ["api.cpp", "refops.cpp", "server.cpp", "kernels_ops.hip", "kernels_cg.hip"]
+SOURCES = ["api.cpp", "refops.cpp", "server.cpp", "kernels_ops.hip", "kernels_cg.hip",
+           "kernels_sl.hip"]
 
 # Packed FP32 instructions are disabled for every HIP compile of this project.
 HIP_FLAGS = [

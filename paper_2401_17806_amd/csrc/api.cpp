@@ -119,6 +119,22 @@ int build_ops(int p, void** host, size_t* bytes) {
 }
 
 // float copy of the operators (built on the host, uploaded once)
+template <int P>
+int build_sl_p(std::vector<unsigned char>* out) {
+    out->assign(sizeof(SlOps<P>), 0);
+    return build_slops<P>(reinterpret_cast<SlOps<P>*>(out->data()));
+}
+
+int build_sl(int p, std::vector<unsigned char>* out) {
+    switch (p) {
+        case 1: return build_sl_p<1>(out);
+        case 2: return build_sl_p<2>(out);
+        case 3: return build_sl_p<3>(out);
+        case 4: return build_sl_p<4>(out);
+        default: return 1;
+    }
+}
+
 size_t ops32_bytes(int p) {
     switch (p) {
         case 1: return sizeof(RefOps32<1>);
@@ -182,6 +198,7 @@ void free_disc(sld_disc_s* d) {
     if (w.host_scal_in) (void)hipHostFree(w.host_scal_in);
     if (w.graph32) (void)hipGraphExecDestroy(w.graph32);
     dfree(d->ops32_dev);
+    dfree(d->sl_dev);
     dfree(w.scal);
     if (w.graph) (void)hipGraphExecDestroy(w.graph);
     if (w.capture) (void)hipStreamDestroy(w.capture);
@@ -554,9 +571,16 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     Uploader up;
     std::vector<unsigned char> h32(ops32_bytes(p));
     round_ops(p, d->ops_host, h32.data());
+    std::vector<unsigned char> hsl;
+    if (build_sl(p, &hsl) != 0) {
+        free_disc(d);
+        sld_set_error("sld_disc_create: semi-Lagrangian projection data failed to build");
+        return SLD_E_INVALID;
+    }
     hipError_t e = up.err;
     if (e == hipSuccess) e = hipMalloc(&d->ops_dev, d->ops_bytes);
     if (e == hipSuccess) e = hipMalloc(&d->ops32_dev, h32.size());
+    if (e == hipSuccess) e = hipMalloc(&d->sl_dev, hsl.size());
     if (e == hipSuccess) e = dalloc(&w.x, nv);
     for (int k = 0; k < 2; ++k) {
         if (e == hipSuccess) e = dalloc(&w.r[k], nv);
@@ -578,6 +602,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     if (e == hipSuccess) {
         up.copy(d->ops_dev, d->ops_host, d->ops_bytes);
         up.copy(d->ops32_dev, h32.data(), h32.size());
+        up.copy(d->sl_dev, hsl.data(), hsl.size());
         up.zero(w.scal, CgScalars::NSCAL * sizeof(double));
         up.zero(w.scal_in, CgScalars::NSCAL * sizeof(double));
         e = up.finish();
@@ -728,6 +753,19 @@ sld_status sld_velocity_correct(sld_disc d, const double* v_star, const double* 
     SLD_REQUIRE_DEVICE(d, "sld_velocity_correct");
     DeviceGuard dg(d->mesh->device);
     SLD_HIP_CHECK(launch_gradient(d, p, v_star, -coef, v, (hipStream_t)stream));
+    return SLD_OK;
+}
+
+sld_status sld_sl_advect(sld_disc d, const double* vbar, const double* q, int32_t nc, double dt,
+                         double* q_out, void* stream) {
+    SLD_REQUIRE(d && vbar && q && q_out, SLD_E_INVALID, "sld_sl_advect: NULL argument");
+    SLD_REQUIRE(nc >= 1 && nc <= 8, SLD_E_INVALID, "sld_sl_advect: nc must be in 1..8");
+    SLD_REQUIRE(std::isfinite(dt), SLD_E_INVALID, "sld_sl_advect: dt must be finite");
+    SLD_REQUIRE(q_out != q && q_out != vbar, SLD_E_INVALID,
+                "sld_sl_advect: q_out must not alias q or vbar");
+    SLD_REQUIRE_DEVICE(d, "sld_sl_advect");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_sl_advect(d, vbar, q, nc, dt, q_out, (hipStream_t)stream));
     return SLD_OK;
 }
 

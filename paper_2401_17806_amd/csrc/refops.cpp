@@ -292,3 +292,33 @@ template int build_refops<1>(RefOps<1>*);
 template int build_refops<2>(RefOps<2>*);
 template int build_refops<3>(RefOps<3>*);
 template int build_refops<4>(RefOps<4>*);
+
+template <int P>
+int build_slops(SlOps<P>* ops) {
+    constexpr int N = SlOps<P>::NPHI, NG = SlOps<P>::NG;
+    const TriRule r = triangle_rule(P + 1);
+    const Basis<P> B;
+    std::vector<ld> phi(size_t(NG) * N);
+    for (int g = 0; g < NG; ++g) B.eval(r.u[g], r.v[g], &phi[size_t(g) * N], nullptr, nullptr);
+    // M_ref = Phi^T W Phi (exact: the integrand has degree 2P); rhs = Phi^T W
+    std::vector<ld> M(size_t(N) * N, 0), R(size_t(N) * NG, 0);
+    for (int g = 0; g < NG; ++g)
+        for (int k = 0; k < N; ++k) {
+            R[size_t(k) * NG + g] = r.w[g] * phi[size_t(g) * N + k];
+            for (int l = 0; l < N; ++l)
+                M[size_t(k) * N + l] += r.w[g] * phi[size_t(g) * N + k] * phi[size_t(g) * N + l];
+        }
+    if (!solve_dense(N, NG, M, R)) return 1;
+    for (int g = 0; g < NG; ++g) {
+        ops->pts[g][0] = (double)r.u[g];
+        ops->pts[g][1] = (double)r.v[g];
+    }
+    for (int k = 0; k < N; ++k)
+        for (int g = 0; g < NG; ++g) ops->proj[k][g] = (double)R[size_t(k) * NG + g];
+    return 0;
+}
+
+template int build_slops<1>(SlOps<1>*);
+template int build_slops<2>(SlOps<2>*);
+template int build_slops<3>(SlOps<3>*);
+template int build_slops<4>(SlOps<4>*);

@@ -74,6 +74,21 @@ void round_refops(const RefOps<P>& in, RefOps32<P>* out) {
         }
 }
 
+// Semi-Lagrangian projection data (Section 3.5): the Gauss rule on T_ref (collapsed
+// Gauss-Legendre, P + 1 points per direction, exact for the degree-2P projection integrand)
+// and proj = M_ref^{-1} Phi^T diag(w), so that the projected coefficients of a field known at
+// the Gauss points are proj * values.
+template <int P>
+struct SlOps {
+    static constexpr int NPHI = (P + 1) * (P + 2) / 2;
+    static constexpr int NG = (P + 1) * (P + 1);
+    double pts[NG][2];
+    double proj[NPHI][NG];
+};
+
+template <int P>
+int build_slops(SlOps<P>* ops);
+
 // Fill ops for degree P (1..4).  Returns 0 on success.
 template <int P>
 int build_refops(RefOps<P>* ops);

@@ -95,6 +95,7 @@ struct sld_disc_s {
     void* ops_dev = nullptr;       // RefOps<p> on the device
     void* ops_host = nullptr;      // RefOps<p> on the host
     void* ops32_dev = nullptr;     // RefOps32<p> on the device (mixed precision)
+    void* sl_dev = nullptr;        // SlOps<p> on the device (semi-Lagrangian projection)
     size_t ops_bytes = 0;
     CgWork cg;
 };
@@ -124,4 +125,6 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s);
 hipError_t launch_rel_init(const sld_disc_s* d, double rtol, int maxit, hipStream_t s);
 hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s);
 hipError_t launch_rel_restart(const sld_disc_s* d, hipStream_t s);
+hipError_t launch_sl_advect(const sld_disc_s* d, const double* vbar, const double* q, int nc,
+                            double dt, double* out, hipStream_t s);
 hipError_t launch_rel_peek(const sld_disc_s* d, int resume, hipStream_t s);

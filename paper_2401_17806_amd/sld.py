@@ -74,6 +74,7 @@ _sig("sld_velocity_correct", [_vp, _vp, _vp, ctypes.c_double, _vp, _vp])
 _sig("sld_cg_solve", [_vp, _vp, _vp, ctypes.POINTER(sld_cg_params),
                       ctypes.POINTER(sld_cg_report), _vp])
 _sig("sld_disc_footprint", [_vp, ctypes.POINTER(ctypes.c_uint64)])
+_sig("sld_sl_advect", [_vp, _vp, _vp, _i32, ctypes.c_double, _vp, _vp])
 _sig("sld_server_create", [_i32, ctypes.c_uint64, _i32, ctypes.POINTER(_vp)])
 _sig("sld_server_submit", [_vp, _vp, _vp, _vp, ctypes.POINTER(sld_cg_params), _vp,
                            ctypes.POINTER(ctypes.c_uint64)])
@@ -88,6 +89,7 @@ EXPORTED = [
     "sld_mesh_destroy", "sld_disc_create", "sld_disc_info", "sld_main_nodes", "sld_dual_nodes",
     "sld_main_weights", "sld_disc_destroy", "sld_schur_apply", "sld_gradient", "sld_divergence",
     "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_disc_footprint",
+    "sld_sl_advect",
     "sld_server_create", "sld_server_submit", "sld_server_poll", "sld_server_stats",
     "sld_server_destroy",
 ]
@@ -294,6 +296,21 @@ class Disc:
         v = ctypes.c_uint64()
         _check(_lib.sld_disc_footprint(self.handle, ctypes.byref(v)))
         return int(v.value)
+
+    def sld_sl_advect(self, vbar, q, dt, out=None, stream=None):
+        """q [ne, nc, N_phi] advected over dt by the velocity vbar [ne, 2, N_phi]."""
+        import torch
+        if q.dim() != 3 or q.shape[0] != self.mesh.ne or q.shape[2] != self.nphi:
+            raise ValueError(f"q must be [{self.mesh.ne}, nc, {self.nphi}]")
+        nc = int(q.shape[1])
+        self._dev(vbar, (self.mesh.ne, 2, self.nphi), "vbar")
+        self._dev(q, tuple(q.shape), "q")
+        if out is None:
+            out = torch.empty_like(q)
+        self._dev(out, tuple(q.shape), "out")
+        _check(_lib.sld_sl_advect(self.handle, _vp(vbar.data_ptr()), _vp(q.data_ptr()), nc,
+                                  float(dt), _vp(out.data_ptr()), self._stream(stream)))
+        return out
 
     def sld_cg_solve(self, b, p=None, rtol=1e-12, maxit=100000, warm_start=False,
                      graph_block=32, profile=False, precision="fp64", inner_rtol=0.5,
