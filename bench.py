@@ -111,6 +111,81 @@ def cpu_baseline(wl, xy, tri, per, b_host, iters=200):
             "seconds": info["seconds"] + t_asm}
 
 
+def sl_bytes_per_tri(nphi: int, nc: int) -> int:
+    # one launch: read the velocity (2 N) and the fields (nc N), write the fields (nc N), plus
+    # the triangle's edge vectors (32 B) and neighbour codes (16 B); cells visited by a walk
+    # are the neighbours' own data, read once per launch algorithmically
+    return 8 * (2 + 2 * nc) * nphi + 48
+
+
+def sl_cpu_baseline(wl, xy, tri, per, vb, q, dt, ntri=96):
+    """The oracle's advection on a bounded sample of triangles, scaled to DOF-updates/s."""
+    from oracle import advect
+    from oracle.mesh import OracleMesh
+    from oracle.operators import OracleDisc
+    od = OracleDisc(OracleMesh(xy, tri, per), wl["p"])
+    ids = np.arange(ntri)
+    t0 = time.perf_counter()
+    advect.sl_advect_rows(od, vb, q, dt, ids)
+    sec = time.perf_counter() - t0
+    return {"value": ntri * q.shape[1] * q.shape[2] / sec, "unit": "DOF-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"the oracle's cell-by-cell walk and projection for {ntri} of the "
+                      f"{q.shape[0]} triangles ({q.shape[1]} fields), single thread"}
+
+
+def bench_sl_advect(args, torch, sld, lattice_mesh, random_fourier_field, nc=3):
+    """One step = one sld_sl_advect launch over the whole mesh (nc fields, CFL 0.5)."""
+    wl = WORKLOADS[args.workload]
+    n, p = wl["n"], wl["p"]
+    xy, tri, per = lattice_mesh(n, seed=wl["seed"])
+    mesh = sld.Mesh(xy, tri, per, device=0)
+    disc = sld.Disc(mesh, p)
+    ne, nphi = mesh.ne, disc.nphi
+    f = random_fourier_field(wl["rhs_seed"], kmax=8)
+    vb_h = np.ascontiguousarray(f(disc.main_nodes()).transpose(0, 2, 1))
+    h = 2 * math.pi / n
+    dt = 0.5 * h / np.abs(vb_h).max()
+    rng = np.random.Generator(np.random.PCG64(wl["rhs_seed"] + 7))
+    q_h = rng.standard_normal((ne, nc, nphi))
+    vb = torch.from_numpy(vb_h).to("cuda:0")
+    q = torch.from_numpy(q_h).to("cuda:0")
+    out = torch.empty_like(q)
+    steps = max(args.steps, 1) * 20
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1) * 5):
+        disc.sld_sl_advect(vb, q, dt, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        disc.sld_sl_advect(vb, q, dt, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_us = 1e3 * e0.elapsed_time(e1) / steps
+    sbytes = sl_bytes_per_tri(nphi, nc) * ne
+    achieved = sbytes / (kernel_us * 1e-6) / 1e9
+    res = {
+        "metric": "semi-Lagrangian advection DOF-updates/s (advected field coefficients)",
+        "value": ne * nc * nphi * steps / elapsed, "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": max(args.warmup, 1) * 5,
+        "ms_per_step": 1e3 * elapsed / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: sl_advect of {nc} fields, CFL 0.5, "
+                               f"{ne} triangles, p={p}", "triangles": ne, "p": p, "fields": nc},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_sl_advect<{p}>", "kernel_us": kernel_us,
+                     "kernel_us_source": "HIP events around the launches on the launch stream",
+                     "bytes_per_launch": sbytes},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = sl_cpu_baseline(wl, xy, tri, per, vb_h, q_h, dt)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +198,8 @@ def main():
                     help="mixed: FP32 CG with FP64 reliable updates (true FP64 residual to rtol)")
     ap.add_argument("--graph-block", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sl-advect", action="store_true",
+                    help="measure the semi-Lagrangian advection kernel instead (3 fields, CFL 0.5)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy MIB MiB device-to-device three times "
                          "(reference kernel for HBM byte counters)")
@@ -137,6 +214,9 @@ def main():
     from paper_2401_17806_amd import sld
     from paper_2401_17806_amd.inputs import lattice_mesh, random_fourier_field
 
+    if args.sl_advect:
+        bench_sl_advect(args, torch, sld, lattice_mesh, random_fourier_field)
+        return
     if args.rtol is None:
         args.rtol = 1e-12 if args.precision == "fp64" else 1e-11
     mixed = args.precision == "mixed"
