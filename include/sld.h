@@ -103,6 +103,24 @@ sld_status sld_main_nodes(sld_disc disc, double* xy_out);
 sld_status sld_dual_nodes(sld_disc disc, double* xy_out);
 /* Host float64 [ne][N_phi]: int_{T_i} phi_k dx (weights of the pressure gauge). */
 sld_status sld_main_weights(sld_disc disc, double* w_out);
+/* sld_ref_operator: host copy of one reference operator of the disc (Section 3.4; the
+ * semi-Lagrangian rule of Section 3.5), float64, row-major, for inspection and tests.
+ *   which  0: S    [3][N_phi][N_phi]  int_{T_ref} grad phi_k grad phi_l by derivative pair
+ *                                     (xi xi, xi eta + eta xi, eta eta)
+ *          1: Sh   [3][N_phi][N_phi]  the same over the sub-triangle of local edge alpha
+ *          2: E    [2][p+1][N_phi]    d_xi / d_eta of phi_l at the nodes of edge alpha
+ *          3: Pt   [2][N_phi][p+1]    sub-triangle correction of edge alpha (device form of
+ *                                     the condensed dual mass inverse)
+ *          4: C    [p+1][p+1]         S0^{-1} M1 (edge condensation)
+ *          5: M1   [p+1][p+1]         1D mass matrix of the edge nodes
+ *          6: w    [N_phi]            int_{T_ref} phi_k
+ *          7: SL points  [(p+1)^2][2] Gauss points of the semi-Lagrangian projection
+ *          8: SL proj    [N_phi][(p+1)^2] M_ref^{-1} Phi^T diag(w)
+ *   alpha  local edge 0..2 (which = 1, 2, 3), ignored otherwise
+ *   host_out may be NULL (size query); *count receives the number of doubles; cap is the
+ *   capacity of host_out in doubles (SLD_E_INVALID if too small). */
+sld_status sld_ref_operator(sld_disc disc, int32_t which, int32_t alpha, double* host_out,
+                            int64_t cap, int64_t* count);
 void sld_disc_destroy(sld_disc disc);
 
 /* ------------------------------------------------------------------ operators (device)

@@ -624,6 +624,64 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     return SLD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+template <int P>
+sld_status ref_operator_p(const sld_disc_s* d, int which, int alpha, std::vector<double>* v) {
+    const RefOps<P>& R = *reinterpret_cast<const RefOps<P>*>(d->ops_host);
+    auto put = [&](const double* a, size_t n) { v->assign(a, a + n); };
+    constexpr int N = RefOps<P>::NPHI, NE = P + 1;
+    switch (which) {
+        case 0: put(&R.S[0][0][0], size_t(3) * N * N); break;
+        case 1: put(&R.Sh[alpha][0][0][0], size_t(3) * N * N); break;
+        case 2: put(&R.E[alpha][0][0][0], size_t(2) * NE * N); break;
+        case 3: put(&R.Pt[alpha][0][0][0], size_t(2) * N * NE); break;
+        case 4: put(&R.C[0][0], size_t(NE) * NE); break;
+        case 5: put(&R.M1[0][0], size_t(NE) * NE); break;
+        case 6: put(&R.w[0], size_t(N)); break;
+        case 7:
+        case 8: {
+            SlOps<P> sl;
+            if (build_slops<P>(&sl) != 0) {
+                sld_set_error("sld_ref_operator: semi-Lagrangian rule failed to build");
+                return SLD_E_INVALID;
+            }
+            if (which == 7) put(&sl.pts[0][0], size_t(SlOps<P>::NG) * 2);
+            else put(&sl.proj[0][0], size_t(N) * SlOps<P>::NG);
+        } break;
+        default:
+            sld_set_error("sld_ref_operator: which must be in 0..8");
+            return SLD_E_INVALID;
+    }
+    return SLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sld_status sld_ref_operator(sld_disc d, int32_t which, int32_t alpha, double* host_out,
+                            int64_t cap, int64_t* count) {
+    SLD_REQUIRE(d && count, SLD_E_INVALID, "sld_ref_operator: NULL argument");
+    SLD_REQUIRE(alpha >= 0 && alpha <= 2, SLD_E_INVALID, "sld_ref_operator: alpha must be 0..2");
+    std::vector<double> v;
+    sld_status st = SLD_E_INVALID;
+    switch (d->p) {
+        case 1: st = ref_operator_p<1>(d, which, alpha, &v); break;
+        case 2: st = ref_operator_p<2>(d, which, alpha, &v); break;
+        case 3: st = ref_operator_p<3>(d, which, alpha, &v); break;
+        case 4: st = ref_operator_p<4>(d, which, alpha, &v); break;
+    }
+    if (st != SLD_OK) return st;
+    *count = (int64_t)v.size();
+    if (!host_out) return SLD_OK;
+    SLD_REQUIRE(cap >= (int64_t)v.size(), SLD_E_INVALID, "sld_ref_operator: cap too small");
+    std::memcpy(host_out, v.data(), sizeof(double) * v.size());
+    return SLD_OK;
+}
+
 sld_status sld_disc_info(sld_disc d, int32_t* p, int32_t* nphi, int32_t* npsi) {
     SLD_REQUIRE(d, SLD_E_INVALID, "sld_disc_info: NULL disc");
     if (p) *p = d->p;

@@ -74,6 +74,7 @@ _sig("sld_velocity_correct", [_vp, _vp, _vp, ctypes.c_double, _vp, _vp])
 _sig("sld_cg_solve", [_vp, _vp, _vp, ctypes.POINTER(sld_cg_params),
                       ctypes.POINTER(sld_cg_report), _vp])
 _sig("sld_disc_footprint", [_vp, ctypes.POINTER(ctypes.c_uint64)])
+_sig("sld_ref_operator", [_vp, _i32, _i32, _c_dp, _i64, ctypes.POINTER(_i64)])
 _sig("sld_sl_advect", [_vp, _vp, _vp, _i32, ctypes.c_double, _vp, _vp])
 _sig("sld_server_create", [_i32, ctypes.c_uint64, _i32, ctypes.POINTER(_vp)])
 _sig("sld_server_submit", [_vp, _vp, _vp, _vp, ctypes.POINTER(sld_cg_params), _vp,
@@ -89,7 +90,7 @@ EXPORTED = [
     "sld_mesh_destroy", "sld_disc_create", "sld_disc_info", "sld_main_nodes", "sld_dual_nodes",
     "sld_main_weights", "sld_disc_destroy", "sld_schur_apply", "sld_gradient", "sld_divergence",
     "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_disc_footprint",
-    "sld_sl_advect",
+    "sld_sl_advect", "sld_ref_operator",
     "sld_server_create", "sld_server_submit", "sld_server_poll", "sld_server_stats",
     "sld_server_destroy",
 ]
@@ -296,6 +297,19 @@ class Disc:
         v = ctypes.c_uint64()
         _check(_lib.sld_disc_footprint(self.handle, ctypes.byref(v)))
         return int(v.value)
+
+    REF_OPERATORS = {"S": 0, "Sh": 1, "E": 2, "Pt": 3, "C": 4, "M1": 5, "w": 6,
+                     "sl_points": 7, "sl_proj": 8}
+
+    def sld_ref_operator(self, which: str, alpha: int = 0) -> np.ndarray:
+        """Host copy of a reference operator (flat float64; see include/sld.h for shapes)."""
+        code = self.REF_OPERATORS[which]
+        cnt = _i64()
+        _check(_lib.sld_ref_operator(self.handle, code, int(alpha), None, 0, ctypes.byref(cnt)))
+        out = np.empty(cnt.value, dtype=np.float64)
+        _check(_lib.sld_ref_operator(self.handle, code, int(alpha),
+                                     out.ctypes.data_as(_c_dp), cnt.value, ctypes.byref(cnt)))
+        return out
 
     def sld_sl_advect(self, vbar, q, dt, out=None, stream=None):
         """q [ne, nc, N_phi] advected over dt by the velocity vbar [ne, 2, N_phi]."""

@@ -97,3 +97,38 @@ def test_disc_keeps_its_mesh_alive():
     d1.close()
     assert d2.dual_nodes().shape[0] == 3 * 25
     d2.close()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_reference_operators_match_oracle_integrals(p):
+    """The library's reference matrices (host copies) against the oracle's own quadrature of
+    the same integrals on T_ref, and its semi-Lagrangian rule and projection."""
+    from oracle import advect, basis
+    from oracle.quadrature import gauss_legendre_01, triangle_rule
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(3, seed=1)
+    d = sld.Disc(sld.Mesh(xy, tri, per, device=-1), p)
+    N, NE = d.nphi, p + 1
+    pts, w = triangle_rule(p + 2)
+    g = basis.grad_phi(p, pts[:, 0], pts[:, 1])  # [q, N, 2]
+    S = np.stack([np.einsum("q,qk,ql->kl", w, g[..., 0], g[..., 0]),
+                  np.einsum("q,qk,ql->kl", w, g[..., 0], g[..., 1]) +
+                  np.einsum("q,qk,ql->kl", w, g[..., 1], g[..., 0]),
+                  np.einsum("q,qk,ql->kl", w, g[..., 1], g[..., 1])])
+    assert np.abs(d.sld_ref_operator("S").reshape(3, N, N) - S).max() < 1e-13
+    wk = np.einsum("q,qk->k", w, basis.phi(p, pts[:, 0], pts[:, 1]))
+    assert np.abs(d.sld_ref_operator("w") - wk).max() < 1e-14
+    verts = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    for alpha in range(3):
+        a, b = verts[alpha], verts[(alpha + 1) % 3]
+        xm = a[None, :] + (np.arange(NE)[:, None] / p) * (b - a)[None, :]
+        E = basis.grad_phi(p, xm[:, 0], xm[:, 1]).transpose(2, 0, 1)  # [2, NE, N]
+        assert np.abs(d.sld_ref_operator("E", alpha).reshape(2, NE, N) - E).max() < 1e-12
+    s, ws = gauss_legendre_01(p + 2)
+    ph = basis.phi(p, s, np.zeros_like(s))[:, :NE]  # edge-0 nodes are main nodes 0..p
+    M1 = np.einsum("q,qm,qn->mn", ws, ph, ph)
+    assert np.abs(d.sld_ref_operator("M1").reshape(NE, NE) - M1).max() < 1e-14
+    sp, _ = advect.sl_rule(p)
+    assert np.abs(d.sld_ref_operator("sl_points").reshape(-1, 2) - sp).max() < 1e-15
+    proj = advect.projection_matrix(p)
+    assert np.abs(d.sld_ref_operator("sl_proj").reshape(N, -1) - proj).max() < 1e-12 * np.abs(proj).max()
