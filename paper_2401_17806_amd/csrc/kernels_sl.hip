@@ -80,24 +80,31 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
             const double d2 = gd.G10 * ux + gd.G11 * uy;
             const double dl[3] = {-(d1 + d2), d1, d2};
             const double lam[3] = {l0, l1, l2};
-            double s_star = 0.0;
+            // the coordinate that reaches zero first (smallest lam_k / dl_k over dl_k > 0;
+            // ties to the lowest k), compared by cross-multiplication; one division, and only
+            // when the segment leaves the cell
             int k_star = -1;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 if (dl[k] > 0.0) {
-                    const double s = lam[k] / dl[k];
-                    if (k_star < 0 || s < s_star) {
-                        s_star = s;
+                    if (k_star < 0) {
                         k_star = k;
+                    } else {
+                        const double lk = k_star == 0 ? lam[0] : (k_star == 1 ? lam[1] : lam[2]);
+                        const double dk = k_star == 0 ? dl[0] : (k_star == 1 ? dl[1] : dl[2]);
+                        if (lam[k] * dk < lk * dl[k]) k_star = k;
                     }
                 }
             }
-            if (k_star < 0 || s_star >= tau) {
+            const double lks = k_star == 0 ? lam[0] : (k_star == 1 ? lam[1] : lam[2]);
+            const double dks = k_star == 0 ? dl[0] : (k_star == 1 ? dl[1] : dl[2]);
+            if (k_star < 0 || lks >= tau * dks) {
                 l0 -= tau * dl[0];
                 l1 -= tau * dl[1];
                 l2 -= tau * dl[2];
                 break;
             }
+            const double s_star = lks / dks;
             if (s_star <= 0.0) break;  // cannot move: stop here
             double nl[3] = {fmax(l0 - s_star * dl[0], 0.0), fmax(l1 - s_star * dl[1], 0.0),
                             fmax(l2 - s_star * dl[2], 0.0)};
