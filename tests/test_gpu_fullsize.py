@@ -41,11 +41,12 @@ def torch_dev():
 _CACHE = {}
 
 
-def _setup(n, p, seed):
-    key = (n, p, seed)
+def _setup(n, p, seed, walls=False):
+    key = (n, p, seed, walls)
     if key not in _CACHE:
         from paper_2401_17806_amd import sld
-        xy, tri, per = lattice_mesh(n, seed=seed)
+        xy, tri, per = lattice_mesh(n, seed=seed, periodic=not walls,
+                                    length=(1.0 if walls else 2 * np.pi))
         od = OracleDisc(OracleMesh(xy, tri, per), p)
         mesh = sld.Mesh(xy, tri, per, device=0)
         _CACHE[key] = (od, mesh, sld.Disc(mesh, p))
@@ -60,14 +61,17 @@ def _rhs(torch, od, disc, n, rhs_seed):
     return disc.sld_pressure_rhs(vt, 1.0 / coef)
 
 
-@pytest.mark.parametrize("n,p,seed", [(128, 3, 2), (512, 3, 3), (256, 4, 1005)])
-def test_fullsize_schur_apply_sampled_rows(torch_dev, n, p, seed):
+@pytest.mark.parametrize("n,p,seed,walls", [(128, 3, 2, False), (512, 3, 3, False),
+                                             (256, 4, 1005, False), (256, 2, 4, True)])
+def test_fullsize_schur_apply_sampled_rows(torch_dev, n, p, seed, walls):
     torch = torch_dev
-    _say(f"[fullsize apply] n={n} p={p}")
-    od, mesh, disc = _setup(n, p, seed)
+    _say(f"[fullsize apply] n={n} p={p} walls={walls}")
+    od, mesh, disc = _setup(n, p, seed, walls)
     x = random_vector((mesh.ne, disc.nphi), seed=500 + n)
     got = disc.sld_schur_apply(torch.from_numpy(x).to("cuda:0")).cpu().numpy()
     ids = np.sort(np.random.default_rng(n).choice(mesh.ne, 256, replace=False))
+    if walls:  # make sure wall triangles are among the samples
+        ids = np.unique(np.concatenate([ids, np.arange(0, 2 * n, 3)]))
     want = solve.schur_rows(od, x, ids)
     rel = np.linalg.norm(got[ids] - want) / np.linalg.norm(want)
     _say(f"    sampled rel L2 {rel:.2e}")
@@ -133,3 +137,29 @@ def test_fullsize_c3_solution_properties(torch_dev):
     _say(f"    mixed vs fp64 rel L2 {d:.2e}")
     assert repm["rel_res_true"] <= 1e-10
     assert d <= 1e-9
+
+
+def test_fullsize_cavity_solve_properties(torch_dev):
+    """256x256x2 walled unit box, p = 2 (the cavity mesh), FP64 solve in the bench
+    configuration: converged, true residual on sampled rows (wall triangles included) at the
+    FP64 floor, zero-mean gauge."""
+    torch = torch_dev
+    _say("[fullsize cavity solve]")
+    od, mesh, disc = _setup(256, 2, 4, walls=True)
+    coef = A_SS * 0.5 * (1.0 / 256)
+    vs = random_fourier_field(104, kmax=8, length=1.0)(od.dual_node_xy()).transpose(0, 2, 1)
+    b = disc.sld_pressure_rhs(torch.from_numpy(np.ascontiguousarray(vs)).to("cuda:0"), 1.0 / coef)
+    p64, rep = disc.sld_cg_solve(b, rtol=1e-12, graph_block=64, maxit=200000)
+    _say("   report", rep)
+    assert rep["converged"]
+    bh = b.cpu().numpy()
+    bh = bh - bh.mean()
+    ph = p64.cpu().numpy()
+    ids = np.unique(np.concatenate([np.arange(0, 512, 2),
+                                    np.random.default_rng(9).choice(mesh.ne, 256, replace=False)]))
+    res = bh[ids] - solve.schur_rows(od, ph, ids)
+    rel = np.linalg.norm(res) / np.linalg.norm(bh[ids])
+    _say(f"    sampled true residual {rel:.2e}")
+    assert rel <= 1e-7
+    w = od.main_weights()
+    assert abs((w * ph).sum()) <= 1e-12 * np.abs(ph).max() * w.sum()
