@@ -55,10 +55,18 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
     constexpr int NG = SlOps<P>::NG;
     constexpr int TB = kSlBlock / NG;  // triangles per block
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    double* sq = reinterpret_cast<double*>(lds_raw);  // [TB][NG][nc]
+    double* sq = reinterpret_cast<double*>(lds_raw);  // [TB][NG][nc] values at the feet
+    double* sv = sq + (size_t)kSlBlock * nc;          // [TB][2][N] velocity of the block's cells
+    double* sf = sv + (size_t)TB * 2 * N;             // [TB][nc][N] fields of the block's cells
     const int tloc = threadIdx.x / NG, g = threadIdx.x - (threadIdx.x / NG) * NG;
     const int64_t tri0 = (int64_t)blockIdx.x * TB;
     const int64_t i = tri0 + tloc;
+    const int64_t nt = (ne - tri0) < TB ? (ne - tri0) : TB;
+    // the block's own cells (where most walks start and, at moderate CFL, end) staged in LDS
+    // with coalesced loads
+    for (int f = threadIdx.x; f < (int)nt * 2 * N; f += kSlBlock) sv[f] = vbar[tri0 * 2 * N + f];
+    for (int f = threadIdx.x; f < (int)nt * nc * N; f += kSlBlock) sf[f] = q[tri0 * nc * N + f];
+    __syncthreads();
     if (tloc < TB && i < ne) {
         int64_t c = i;
         double l1 = sl->pts[g][0], l2 = sl->pts[g][1];
@@ -68,7 +76,8 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
             double phi[N];
             eval_phi<P>(l1, l2, phi);
             double ux = 0.0, uy = 0.0;
-            const double* vc = vbar + c * 2 * N;
+            const bool own = c >= tri0 && c < tri0 + nt;
+            const double* vc = own ? sv + (c - tri0) * 2 * N : vbar + c * 2 * N;
 #pragma unroll
             for (int l = 0; l < N; ++l) {
                 ux = fma(vc[l], phi[l], ux);
@@ -131,7 +140,8 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
         }
         double phi[N];
         eval_phi<P>(l1, l2, phi);
-        const double* qc = q + c * (int64_t)nc * N;
+        const double* qc = (c >= tri0 && c < tri0 + nt) ? sf + (c - tri0) * nc * N
+                                                        : q + c * (int64_t)nc * N;
         for (int cmp = 0; cmp < nc; ++cmp) {
             double v = 0.0;
 #pragma unroll
@@ -141,7 +151,6 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
     }
     __syncthreads();
     // projection onto the main basis of each starting triangle (fixed summation order)
-    const int64_t nt = (ne - tri0) < TB ? (ne - tri0) : TB;
     const int nout = (int)nt * nc * N;
     for (int f = threadIdx.x; f < nout; f += kSlBlock) {
         const int t = f / (nc * N);
@@ -156,17 +165,21 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
 
 }  // namespace
 
-size_t sl_lds_bytes(int nc) { return sizeof(double) * (size_t)kSlBlock * (size_t)nc; }
+template <int P>
+size_t sl_lds_bytes(int nc) {
+    constexpr int N = RefOps<P>::NPHI, TB = kSlBlock / SlOps<P>::NG;
+    return sizeof(double) * ((size_t)kSlBlock * nc + (size_t)TB * (2 + nc) * N);
+}
 
 hipError_t launch_sl_advect(const sld_disc_s* d, const double* vbar, const double* q, int nc,
                             double dt, double* out, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
-    const size_t lds = sl_lds_bytes(nc);
     switch (d->p) {
 #define SLD_SL(PP)                                                                               \
     case PP: {                                                                                   \
         constexpr int TB = kSlBlock / SlOps<PP>::NG;                                             \
         const unsigned nb = (unsigned)((m->ne + TB - 1) / TB);                                   \
+        const size_t lds = sl_lds_bytes<PP>(nc);                                                 \
         hipLaunchKernelGGL(k_sl_advect<PP>, dim3(nb), dim3(kSlBlock), lds, s,                    \
                            reinterpret_cast<const SlOps<PP>*>(d->sl_dev), m->geo, m->nbr, m->ne, \
                            vbar, q, nc, dt, out);                                                \
