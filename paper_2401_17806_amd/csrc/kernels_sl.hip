@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
     double* sq = reinterpret_cast<double*>(lds_raw);  // [TB][NG][nc] values at the feet
     double* sv = sq + (size_t)kSlBlock * nc;          // [TB][2][N] velocity of the block's cells
     double* sf = sv + (size_t)TB * 2 * N;             // [TB][nc][N] fields of the block's cells
+    double* sp = sf + (size_t)TB * nc * N;            // [N][NG] projection matrix
     const int tloc = threadIdx.x / NG, g = threadIdx.x - (threadIdx.x / NG) * NG;
     const int64_t tri0 = (int64_t)blockIdx.x * TB;
     const int64_t i = tri0 + tloc;
@@ -66,6 +67,7 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
     // with coalesced loads
     for (int f = threadIdx.x; f < (int)nt * 2 * N; f += kSlBlock) sv[f] = vbar[tri0 * 2 * N + f];
     for (int f = threadIdx.x; f < (int)nt * nc * N; f += kSlBlock) sf[f] = q[tri0 * nc * N + f];
+    for (int f = threadIdx.x; f < N * NG; f += kSlBlock) sp[f] = (&sl->proj[0][0])[f];
     __syncthreads();
     if (tloc < TB && i < ne) {
         int64_t c = i;
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
         const int cmp = rem / N, k = rem - (rem / N) * N;
         double s = 0.0;
 #pragma unroll
-        for (int gg = 0; gg < NG; ++gg) s = fma(sl->proj[k][gg], sq[(t * NG + gg) * nc + cmp], s);
+        for (int gg = 0; gg < NG; ++gg) s = fma(sp[k * NG + gg], sq[(t * NG + gg) * nc + cmp], s);
         out[(tri0 + t) * nc * N + rem] = s;
     }
 }
@@ -168,7 +170,8 @@ __global__ __launch_bounds__(kSlBlock) void k_sl_advect(const SlOps<P>* __restri
 template <int P>
 size_t sl_lds_bytes(int nc) {
     constexpr int N = RefOps<P>::NPHI, TB = kSlBlock / SlOps<P>::NG;
-    return sizeof(double) * ((size_t)kSlBlock * nc + (size_t)TB * (2 + nc) * N);
+    return sizeof(double) * ((size_t)kSlBlock * nc + (size_t)TB * (2 + nc) * N +
+                             (size_t)N * SlOps<P>::NG);
 }
 
 hipError_t launch_sl_advect(const sld_disc_s* d, const double* vbar, const double* q, int nc,
