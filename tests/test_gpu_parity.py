@@ -210,3 +210,37 @@ def test_mixed_precision_solution_parity(torch_dev, n, p, periodic):
     assert rep["outer_iters"] >= 1
     assert rep["rel_res_true"] < 1e-10
     assert _rel(p_gpu.cpu().numpy(), x_or) <= SOLVE_TOL
+
+
+@pytest.mark.parametrize("periodic,p", [(True, 2), (True, 4), (False, 3)])
+def test_parity_on_shuffled_unstructured_numbering(torch_dev, periodic, p):
+    """The same physical mesh with its triangles in random order and each triangle's vertices
+    cyclically rotated (so no triangle numbering or local-edge pattern of the lattice
+    survives): apply and solve still match the oracle on that numbering."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    _say(f"[shuffled] periodic={periodic} p={p}")
+    xy, tri, per = lattice_mesh(9, seed=31, periodic=periodic,
+                                length=(2 * np.pi if periodic else 1.0))
+    rng = np.random.default_rng(17)
+    order = rng.permutation(tri.shape[0])
+    rot = rng.integers(0, 3, size=tri.shape[0])
+    tri2 = np.stack([np.roll(t, -r) for t, r in zip(tri[order], rot)]).astype(np.int32)
+    vperm = rng.permutation(xy.shape[0])          # renumber the vertices too
+    inv = np.empty_like(vperm)
+    inv[vperm] = np.arange(vperm.size)
+    xy2 = xy[vperm]
+    tri2 = inv[tri2].astype(np.int32)
+    od = OracleDisc(OracleMesh(xy2, tri2, per), p)
+    K = solve.assemble_K(od)
+    disc = sld.Disc(sld.Mesh(xy2, tri2, per, device=0), p)
+    x = random_vector((od.mesh.ne, disc.nphi), seed=61)
+    got = disc.sld_schur_apply(_to(torch, x)).cpu().numpy()
+    assert _rel(got, solve.schur_apply(K, x)) <= APPLY_TOL
+    f = random_fourier_field(19, kmax=3, length=(2 * np.pi if periodic else 1.0))
+    b = solve.divergence(od, f(od.dual_node_xy()).transpose(0, 2, 1))
+    x_or, info = solve.cg(K, b, tol=1e-13)
+    x_or = solve.gauge(od, x_or)
+    p_gpu, rep = disc.sld_cg_solve(_to(torch, b), rtol=1e-13, maxit=20000, graph_block=8)
+    assert rep["converged"]
+    assert _rel(p_gpu.cpu().numpy(), x_or) <= SOLVE_TOL
