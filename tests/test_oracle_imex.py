@@ -1,0 +1,164 @@
+"""Pins of the oracle's grid transfers (eqs. d2m, m2d) and of its R = 0 semi-Lagrangian IMEX
+step (Section 4) against what the mathematics fixes:
+  * a global polynomial of degree <= p lies in both spaces, so L_md reproduces its dual
+    interpolant (wall cells included) and L_dm(L_md(.)) is the identity on it;
+  * L_md and L_dm are L2 projections: the residual is orthogonal to every test function of the
+    target space, checked with a finer quadrature than the operators use;
+  * the viscous solve (Mbar - c K) x = Mbar f with c > 0 does not increase the mass-norm
+    energy (fails for the wrong sign of K);
+  * a fluid at rest stays at rest; the step's velocity is discretely divergence-free;
+  * Taylor-Green vortex: first-order convergence in time at fixed CFL (R = 0 is Euler).
+"""
+import numpy as np
+import pytest
+
+from oracle import basis, imex, solve
+from oracle.mesh import OracleMesh
+from oracle.operators import OracleDisc
+from oracle.quadrature import triangle_rule
+from paper_2401_17806_amd.inputs import lattice_mesh, random_vector
+
+
+def _disc(n, p, periodic=True, seed=3):
+    xy, tri, per = lattice_mesh(n, seed=seed, periodic=periodic,
+                                length=(2 * np.pi if periodic else 1.0))
+    return OracleDisc(OracleMesh(xy, tri, per), p)
+
+
+def _poly(p, seed):
+    c = np.random.default_rng(seed).normal(size=(2, basis.n_phi(p)))
+
+    def f(xy):
+        x, y = xy[..., 0], xy[..., 1]
+        mons = [x ** i * y ** j for j in range(p + 1) for i in range(p + 1 - j)]
+        return np.stack([sum(c[k, m] * mons[m] for m in range(len(mons))) for k in range(2)], -1)
+    return f
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_transfers_reproduce_global_polynomials(p):
+    d = _disc(4, p, periodic=False)
+    f = _poly(p, 10 + p)
+    vm = np.ascontiguousarray(f(d.main_node_xy()).transpose(0, 2, 1))
+    vd = imex.main_to_dual(d, vm)
+    want = imex.dual_interpolant(d, f)
+    inner = d.mesh.interior
+    half = np.array([a + b <= p for (a, b) in basis.dual_node_ab(p)])
+    scale = np.nanmax(np.abs(want))  # wall cells have no right-half nodes (NaN positions)
+    assert np.abs(vd[inner] - want[inner]).max() <= 1e-12 * scale
+    assert np.abs(vd[~inner][:, :, half] - want[~inner][:, :, half]).max() <= 1e-12 * scale
+    assert np.all(vd[~inner][:, :, ~half] == 0.0)
+    back = imex.dual_to_main(d, vd)
+    assert np.abs(back - vm).max() <= 1e-12 * scale
+
+
+def _sub_points(d, n_q):
+    """Finer-rule points on both halves of every dual cell: (x [nd, q, 2] per side, psi, jac)."""
+    m = d.mesh
+    pts, w = triangle_rule(n_q)
+    u, v = pts[:, 0], pts[:, 1]
+    Rs = np.where(m.interior, m.right, m.left)
+    out = []
+    for side, b0 in ((0, m.centroid[m.left]), (1, m.centroid[Rs] - m.shift)):
+        x = b0[:, None] + u[None, :, None] * (m.A - b0)[:, None] + v[None, :, None] * (m.B - b0)[:, None]
+        dd, ee = m.A - b0, m.B - b0
+        jac = np.abs(dd[:, 0] * ee[:, 1] - dd[:, 1] * ee[:, 0])
+        if side == 0:
+            ps = basis.psi(d.p, np.broadcast_to(u, (m.nd, u.size)), np.broadcast_to(v, (m.nd, v.size)))
+            tri = m.left
+        else:
+            jac = jac * m.interior
+            ps = basis.psi(d.p, np.broadcast_to(1.0 - v, (m.nd, v.size)),
+                           np.broadcast_to(1.0 - u, (m.nd, u.size)))
+            tri = Rs
+            x = x + m.shift[:, None]  # r's own frame for its main polynomial
+        out.append((x, ps, jac, tri, w))
+    return out
+
+
+@pytest.mark.parametrize("p,periodic", [(2, True), (3, False)])
+def test_transfers_are_l2_projections(p, periodic):
+    d = _disc(4, p, periodic=periodic)
+    m = d.mesh
+    vm = random_vector((m.ne, 2, d.nphi), seed=40 + p)
+    vd = imex.main_to_dual(d, vm)
+    # L_md: int_{R_j} psi_k (vhat_j - vbar) = 0 for every dual DOF k of cell j
+    res = np.zeros((m.nd, 2, d.npsi))
+    for x, ps, jac, tri, w in _sub_points(d, d.p + 4):
+        ph = np.stack([d.phi_phys(int(i), x[e]) for e, i in enumerate(tri)])  # [nd, q, Nphi]
+        diff = np.einsum("eqk,eck->eqc", ps, vd) - np.einsum("eql,ecl->eqc", ph, vm[tri])
+        res += np.einsum("q,e,eqk,eqc->eck", w, jac, ps, diff)
+    inner = m.interior
+    half = np.array([a + b <= p for (a, b) in basis.dual_node_ab(p)])
+    scale = np.abs(vm).max() * m.area.max()
+    assert np.abs(res[inner]).max() <= 1e-12 * scale
+    if (~inner).any():
+        assert np.abs(res[~inner][:, :, half]).max() <= 1e-12 * scale
+    # L_dm: int_{T_i} phi_k (vbar_i - vhat) = 0 for every main DOF k of triangle i
+    vdr = random_vector((m.nd, 2, d.npsi), seed=50 + p)
+    vdr[np.broadcast_to((~inner)[:, None, None] & (~half)[None, None, :], vdr.shape)] = 0.0
+    vb = imex.dual_to_main(d, vdr)
+    res2 = np.zeros((m.ne, 2, d.nphi))
+    for x, ps, jac, tri, w in _sub_points(d, d.p + 4):
+        for e in range(m.nd):
+            if jac[e] == 0.0:
+                continue
+            i = int(tri[e])
+            ph = d.phi_phys(i, x[e])  # [q, Nphi]
+            diff = ph @ vb[i].T - ps[e] @ vdr[e].T  # [q, 2]
+            res2[i] += np.einsum("q,qk,qc->ck", w * jac[e], ph, diff)
+    assert np.abs(res2).max() <= 1e-12 * np.abs(vdr).max() * m.area.max()
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_viscous_solve_dissipates(p):
+    d = _disc(5, p)
+    K = solve.assemble_K(d)
+    f = random_vector((d.mesh.ne, 1, d.nphi), seed=7)
+    x = imex.viscous_solve(d, K, f, 0.05)
+    M = imex.mass_matrix(d)
+    ef = float(f.reshape(-1) @ (M @ f.reshape(-1)))
+    ex = float(x.reshape(-1) @ (M @ x.reshape(-1)))
+    assert ex < ef
+    # constants are in the kernel of K, so they pass unchanged
+    one = np.ones_like(f)
+    assert np.abs(imex.viscous_solve(d, K, one, 0.05) - 1.0).max() <= 1e-12
+
+
+def test_rest_state_stays_at_rest():
+    d = _disc(3, 2)
+    K = solve.assemble_K(d)
+    v = np.zeros((d.mesh.nd, 2, d.npsi))
+    vn, pi, _ = imex.imex_step(d, K, v, 0.3, 1e-2)
+    assert np.abs(vn).max() == 0.0 and np.abs(pi).max() <= 1e-14
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_step_velocity_is_divergence_free(p):
+    d = _disc(4, p)
+    K = solve.assemble_K(d)
+    v = imex.dual_interpolant(d, lambda xy: imex.tgv_velocity(xy, 0.0, 1e-2))
+    vn, pi, st = imex.imex_step(d, K, v, 0.2, 1e-2)
+    dv_star = np.linalg.norm(solve.divergence(d, st["vs"]))
+    dv = np.linalg.norm(solve.divergence(d, vn))
+    assert dv_star > 1e-3
+    assert dv <= 1e-10 * dv_star
+
+
+def test_tgv_first_order_in_time():
+    """R = 0 at CFL 0.5 (dt = h / 2), nu = 1e-2, t_end = 2 pi / 6: the velocity error against
+    the decaying vortex halves when h and dt halve (Euler in time dominates)."""
+    nu, p = 1e-2, 2
+    errs = []
+    for n in (6, 12):
+        d = _disc(n, p, seed=n)
+        K = solve.assemble_K(d)
+        dt = 0.5 * 2 * np.pi / n
+        steps = n // 3
+        v = imex.dual_interpolant(d, lambda xy: imex.tgv_velocity(xy, 0.0, nu))
+        for _ in range(steps):
+            v, _, _ = imex.imex_step(d, K, v, dt, nu)
+        errs.append(imex.dual_l2_error(d, v, lambda xy: imex.tgv_velocity(xy, steps * dt, nu)))
+    order = np.log2(errs[0] / errs[1])
+    assert 0.8 <= order <= 1.4, (errs, order)
+    assert errs[1] < 0.35
