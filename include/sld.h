@@ -116,7 +116,11 @@ sld_status sld_main_weights(sld_disc disc, double* w_out);
  *          6: w    [N_phi]            int_{T_ref} phi_k
  *          7: SL points  [(p+1)^2][2] Gauss points of the semi-Lagrangian projection
  *          8: SL proj    [N_phi][(p+1)^2] M_ref^{-1} Phi^T diag(w)
- *   alpha  local edge 0..2 (which = 1, 2, 3), ignored otherwise
+ *          9: Mref [N_phi][N_phi]     int_{T_ref} phi_k phi_l (Mbar_i = 2|T_i| Mref)
+ *         10: Ldm  [N_phi][N_phi]     dual -> main projection of the half of the dual cell of
+ *                                     edge alpha: Mref^{-1} int_{T^alpha} phi_k phi_n(zeta),
+ *                                     n the sub-triangle's nodes (eq. d2m)
+ *   alpha  local edge 0..2 (which = 1, 2, 3, 10), ignored otherwise
  *   host_out may be NULL (size query); *count receives the number of doubles; cap is the
  *   capacity of host_out in doubles (SLD_E_INVALID if too small). */
 sld_status sld_ref_operator(sld_disc disc, int32_t which, int32_t alpha, double* host_out,
@@ -207,6 +211,68 @@ typedef struct {
 
 sld_status sld_cg_solve(sld_disc disc, const double* b, double* p, const sld_cg_params* params,
                         sld_cg_report* report, void* stream);
+
+/* ------------------------------------------------------------------ IMEX time step (Section 4)
+ * Grid transfers (eqs. d2m and m2d), the L2 projections between the main and the dual space
+ * through the operator U of eq. u (U_ij[k][l] = int over T_ij of psi_k^(j) phi_l^(i)):
+ *   sld_dual_to_main: out_i = Mbar_i^{-1} sum_{j in S_i} U_ij^T v_j
+ *     v   device float64 [nd][nc][N_psi], out device float64 [ne][nc][N_phi]
+ *   sld_main_to_dual: out_j = Mhat_j^{-1} (U_lj v_l + U_rj v_r)
+ *     v   device float64 [ne][nc][N_phi], out device float64 [nd][nc][N_psi]; a wall edge's
+ *     dual cell is its left half alone: the DOFs of the absent right half are set to 0
+ * 1 <= nc <= 8; out must not alias v.  Asynchronous on `stream`.  SLD_E_INVALID for bad
+ * arguments. */
+sld_status sld_dual_to_main(sld_disc disc, const double* v, int32_t nc, double* out, void* stream);
+sld_status sld_main_to_dual(sld_disc disc, const double* v, int32_t nc, double* out, void* stream);
+
+/* Viscous (implicit diffusion) solve of the IMEX stages, the advection-diffusion scheme of
+ * eq. ad5 with the main-grid Laplacian K of eq. pressure_final:
+ *   (Mbar - c K) x = Mbar f,   c = a_ss dt nu >= 0   (c = 0: x = f)
+ * f, x device float64 [ne][N_phi] (may alias).  Conjugate gradients on the positive definite
+ * (1/c) Mbar - K, warm-started from f, with the iteration kernel of sld_cg_solve; params as
+ * there (precision must be 0: FP64; warm_start is ignored); the stopping rule is relative to
+ * ||(1/c) Mbar f||.  Blocks like sld_cg_solve.  SLD_E_NOCONV / SLD_E_BREAKDOWN as there. */
+sld_status sld_viscous_solve(sld_disc disc, const double* f, double c, double* x,
+                             const sld_cg_params* params, sld_cg_report* report, void* stream);
+
+/* sld_state: the device workspace of sld_imex_step on one disc (velocity on the main grid,
+ * its semi-Lagrangian projection, the viscous solution, the dual intermediate velocity and a
+ * right-hand side: 7 ne N_phi + 2 nd N_psi doubles).  Destroy it before its disc.  Steps on
+ * one state (and any solve on its disc) must not overlap. */
+typedef struct sld_state_s* sld_state;
+sld_status sld_state_create(sld_disc disc, sld_state* out);
+void sld_state_destroy(sld_state state);
+
+typedef struct {
+    double nu;                /* kinematic viscosity, >= 0 (0: no viscous solve) */
+    int32_t R;                /* IMEX member (appendix tableaux): 0 = one stage, first order;
+                                 only R = 0 is built */
+    sld_cg_params pressure;   /* the pressure solve (FP64 or mixed) */
+    sld_cg_params viscous;    /* the two viscous solves (FP64) */
+} sld_imex_params;
+
+typedef struct {
+    sld_cg_report pressure;
+    sld_cg_report viscous[2]; /* one per velocity component */
+    double seconds;           /* wall time of the step on the host */
+} sld_imex_report;
+
+/* One step of the semi-Lagrangian IMEX scheme for incompressible Navier-Stokes (Section 4),
+ * R = 0 (a_ss = 1), on a periodic mesh, without gravity or buoyancy sources:
+ *   1. vbar = L_dm(v)                                      (eq. d2m)
+ *   2. vbar_F = sld_sl_advect of vbar by itself over dt     (Section 3.5, eq. intstage)
+ *   3. (Mbar - a_ss dt nu K) vbar* = Mbar vbar_F per component  (eq. ad5)
+ *   4. v* = L_md(vbar*)                                     (eq. m2d)
+ *   5. K p = (1 / (a_ss dt)) D v*, int p = 0                (eq. pressure_IMEX)
+ *   6. v = v* - a_ss dt Mhat^{-1} (Q_l p_l + Q_r p_r)       (eq. nc.2)
+ * v  device float64 [nd][2][N_psi]: in the velocity at t, out at t + dt.
+ * p  device float64 [ne][N_phi]: out the pressure of the step (in: the initial guess when
+ *    params->pressure.warm_start).  v and p must not alias.
+ * Blocks until the step ends (synchronises `stream`).  SLD_E_INVALID for bad
+ * arguments, R != 0 or a mesh with walls; a solver status (SLD_E_NOCONV, ...) stops the step
+ * where it failed and is returned with the report filled so far. */
+sld_status sld_imex_step(sld_state state, const sld_imex_params* params, double dt, double* v,
+                         double* p, sld_imex_report* report, void* stream);
 
 /* ------------------------------------------------------------------ serving
  * Continuous batching of independent pressure solves (the paper's pressure stage of

@@ -201,6 +201,7 @@ void free_disc(sld_disc_s* d) {
     dfree(d->sl_dev);
     dfree(w.scal);
     if (w.graph) (void)hipGraphExecDestroy(w.graph);
+    if (w.graph_shift) (void)hipGraphExecDestroy(w.graph_shift);
     if (w.capture) (void)hipStreamDestroy(w.capture);
     if (w.host_scal) (void)hipHostFree(w.host_scal);
     for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
@@ -651,8 +652,10 @@ sld_status ref_operator_p(const sld_disc_s* d, int which, int alpha, std::vector
             if (which == 7) put(&sl.pts[0][0], size_t(SlOps<P>::NG) * 2);
             else put(&sl.proj[0][0], size_t(N) * SlOps<P>::NG);
         } break;
+        case 9: put(&R.Mref[0][0], size_t(N) * N); break;
+        case 10: put(&R.Ldm[alpha][0][0], size_t(N) * N); break;
         default:
-            sld_set_error("sld_ref_operator: which must be in 0..8");
+            sld_set_error("sld_ref_operator: which must be in 0..10");
             return SLD_E_INVALID;
     }
     return SLD_OK;
@@ -831,8 +834,9 @@ sld_status sld_sl_advect(sld_disc d, const double* vbar, const double* q, int32_
 
 namespace {
 
-// Capture one block of gb CG iterations (FP64 or the FP32 inner solve) into a graph.
-hipError_t capture_block(sld_disc_s* d, bool fp32, int gb, hipGraphExec_t* out) {
+// Capture one block of gb CG iterations (FP64, FP64 mass-shifted, or the FP32 inner solve)
+// into a graph.
+hipError_t capture_block(sld_disc_s* d, bool fp32, bool shift, int gb, hipGraphExec_t* out) {
     CgWork& w = d->cg;
     if (*out) {
         hipError_t e = hipGraphExecDestroy(*out);
@@ -845,7 +849,8 @@ hipError_t capture_block(sld_disc_s* d, bool fp32, int gb, hipGraphExec_t* out) 
     if (e != hipSuccess) return e;
     hipError_t ce = hipSuccess;
     for (int k = 0; k < gb && ce == hipSuccess; ++k)
-        ce = fp32 ? launch_cg_step32(d, k & 1, w.capture) : launch_cg_step(d, k & 1, w.capture);
+        ce = fp32 ? launch_cg_step32(d, k & 1, w.capture)
+                  : launch_cg_step(d, k & 1, shift, w.capture);
     e = hipStreamEndCapture(w.capture, &g);
     if (ce != hipSuccess) return ce;
     if (e != hipSuccess) return e;
@@ -860,19 +865,19 @@ struct IterStats {
 };
 
 // Run CG iterations until the device flags DONE in `scal` (host mirror `hs`).
-sld_status run_iterations(sld_disc_s* d, bool fp32, int gb, bool prof, hipStream_t s, double* scal,
-                          double* hs, IterStats* st) {
+sld_status run_iterations(sld_disc_s* d, bool fp32, bool shift, int gb, bool prof, hipStream_t s,
+                          double* scal, double* hs, IterStats* st) {
     typedef CgScalars S;
     CgWork& w = d->cg;
-    hipGraphExec_t& graph = fp32 ? w.graph32 : w.graph;
-    int& graph_block = fp32 ? w.graph32_block : w.graph_block;
+    hipGraphExec_t& graph = fp32 ? w.graph32 : (shift ? w.graph_shift : w.graph);
+    int& graph_block = fp32 ? w.graph32_block : (shift ? w.graph_shift_block : w.graph_block);
     if (prof && w.events.size() < 2) {
         for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
         w.events.assign(2, nullptr);
         for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
     }
     if (graph == nullptr || graph_block != gb) {
-        SLD_HIP_CHECK(capture_block(d, fp32, gb, &graph));
+        SLD_HIP_CHECK(capture_block(d, fp32, shift, gb, &graph));
         graph_block = gb;
     }
     int launched = 0;
@@ -904,7 +909,7 @@ sld_status run_block(sld_disc_s* d, int gb, hipStream_t s, IterStats* st) {
     typedef CgScalars S;
     CgWork& w = d->cg;
     if (w.graph32 == nullptr || w.graph32_block != gb) {
-        SLD_HIP_CHECK(capture_block(d, true, gb, &w.graph32));
+        SLD_HIP_CHECK(capture_block(d, true, false, gb, &w.graph32));
         w.graph32_block = gb;
     }
     SLD_HIP_CHECK(hipGraphLaunch(w.graph32, s));
@@ -917,12 +922,10 @@ sld_status run_block(sld_disc_s* d, int gb, hipStream_t s, IterStats* st) {
     return SLD_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_params* prm,
-                        sld_cg_report* rep, void* stream) {
+// CG driver.  sigma = 0: the pressure system K p = b; sigma > 0: the viscous system
+// (sigma Mbar - K) p = -b (FP64 only).
+sld_status cg_solve_impl(sld_disc d, const double* b, double* p, const sld_cg_params* prm,
+                         sld_cg_report* rep, void* stream, double sigma) {
     SLD_REQUIRE(d && b && p && prm, SLD_E_INVALID, "sld_cg_solve: NULL argument");
     SLD_REQUIRE(prm->rtol > 0 && std::isfinite(prm->rtol), SLD_E_INVALID,
                 "sld_cg_solve: rtol must be positive");
@@ -932,6 +935,8 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
     SLD_REQUIRE(prm->precision == 0 || prm->precision == 1, SLD_E_INVALID,
                 "sld_cg_solve: precision must be 0 (FP64) or 1 (mixed)");
     const bool mixed = prm->precision == 1;
+    const bool shift = sigma > 0.0;
+    SLD_REQUIRE(!(mixed && shift), SLD_E_INVALID, "viscous solves run in FP64 only");
     if (mixed) {
         SLD_REQUIRE(prm->inner_rtol > 0 && prm->inner_rtol < 1, SLD_E_INVALID,
                     "sld_cg_solve: inner_rtol must be in (0, 1)");
@@ -944,13 +949,13 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
     const auto t0 = std::chrono::steady_clock::now();
     CgWork& w = d->cg;
     typedef CgScalars S;
-    SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, s));
+    SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, sigma, s));
     IterStats st;
     int outer = 0, status = 0;  // status: 1 converged, 2 no convergence, 3 breakdown
     double rr = 0, bb = 0;
     if (!mixed) {
-        sld_status e = run_iterations(d, false, prm->graph_block, prm->profile != 0, s, w.scal,
-                                      w.host_scal, &st);
+        sld_status e = run_iterations(d, false, shift, prm->graph_block, prm->profile != 0, s,
+                                      w.scal, w.host_scal, &st);
         if (e != SLD_OK) return e;
         rr = w.host_scal[S::RR];
         bb = w.host_scal[S::BB];
@@ -1023,7 +1028,7 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
         }
         st.iters = total;
     }
-    SLD_HIP_CHECK(launch_cg_finish(d, p, s));
+    SLD_HIP_CHECK(launch_cg_finish(d, p, sigma, s));
     SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
                                  hipMemcpyDeviceToHost, s));
     SLD_HIP_CHECK(hipStreamSynchronize(s));
@@ -1049,6 +1054,182 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
         return SLD_E_NOCONV;
     }
     return SLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_params* prm,
+                        sld_cg_report* rep, void* stream) {
+    return cg_solve_impl(d, b, p, prm, rep, stream, 0.0);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- IMEX step (Section 4)
+
+struct sld_state_s {
+    sld_disc disc = nullptr;
+    double* vbar = nullptr;   // [ne][2][N] velocity on the main grid
+    double* vfoot = nullptr;  // [ne][2][N] its semi-Lagrangian projection
+    double* vsbar = nullptr;  // [2][ne][N] viscous solution, component-major
+    double* vs = nullptr;     // [nd][2][Npsi] the intermediate dual velocity v*
+    double* b = nullptr;      // [ne][N] right-hand side (viscous, then pressure)
+};
+
+namespace {
+
+void free_state(sld_state_s* st) {
+    if (!st) return;
+    dfree(st->vbar);
+    dfree(st->vfoot);
+    dfree(st->vsbar);
+    dfree(st->vs);
+    dfree(st->b);
+    delete st;
+}
+
+// (Mbar - c K) x = Mbar f for one [ne][N] field (f read through strides); x [ne][N].
+sld_status viscous_field(sld_disc d, const double* f, int64_t f_is, int64_t f_cs, int comp,
+                         double c, double* x, double* bbuf, const sld_cg_params* prm,
+                         sld_cg_report* rep, hipStream_t s) {
+    const double sigma = 1.0 / c;
+    // b = -sigma Mbar f (the CG runs -(K - sigma Mbar) x = -b); x = f is the initial guess
+    SLD_HIP_CHECK(launch_mass_rhs(d, f, f_is, f_cs, comp, -sigma, bbuf, x, s));
+    sld_cg_params q = *prm;
+    q.warm_start = 1;
+    return cg_solve_impl(d, bbuf, x, &q, rep, s, sigma);
+}
+
+}  // namespace
+
+extern "C" {
+
+sld_status sld_dual_to_main(sld_disc d, const double* v, int32_t nc, double* out, void* stream) {
+    SLD_REQUIRE(d && v && out, SLD_E_INVALID, "sld_dual_to_main: NULL argument");
+    SLD_REQUIRE(nc >= 1 && nc <= 8, SLD_E_INVALID, "sld_dual_to_main: nc must be in 1..8");
+    SLD_REQUIRE(v != out, SLD_E_INVALID, "sld_dual_to_main: out must not alias v");
+    SLD_REQUIRE_DEVICE(d, "sld_dual_to_main");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_dual_to_main(d, v, nc, out, int64_t(nc) * d->nphi, d->nphi,
+                                      (hipStream_t)stream));
+    return SLD_OK;
+}
+
+sld_status sld_main_to_dual(sld_disc d, const double* v, int32_t nc, double* out, void* stream) {
+    SLD_REQUIRE(d && v && out, SLD_E_INVALID, "sld_main_to_dual: NULL argument");
+    SLD_REQUIRE(nc >= 1 && nc <= 8, SLD_E_INVALID, "sld_main_to_dual: nc must be in 1..8");
+    SLD_REQUIRE(v != out, SLD_E_INVALID, "sld_main_to_dual: out must not alias v");
+    SLD_REQUIRE_DEVICE(d, "sld_main_to_dual");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_main_to_dual(d, v, nc, int64_t(nc) * d->nphi, d->nphi, out,
+                                      (hipStream_t)stream));
+    return SLD_OK;
+}
+
+sld_status sld_viscous_solve(sld_disc d, const double* f, double c, double* x,
+                             const sld_cg_params* prm, sld_cg_report* rep, void* stream) {
+    SLD_REQUIRE(d && f && x && prm, SLD_E_INVALID, "sld_viscous_solve: NULL argument");
+    SLD_REQUIRE(std::isfinite(c) && c >= 0.0, SLD_E_INVALID,
+                "sld_viscous_solve: c must be finite and >= 0");
+    SLD_REQUIRE(prm->precision == 0, SLD_E_INVALID, "sld_viscous_solve: precision must be 0 (FP64)");
+    SLD_REQUIRE_DEVICE(d, "sld_viscous_solve");
+    DeviceGuard dg(d->mesh->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (c == 0.0) {
+        if (x != f)
+            SLD_HIP_CHECK(hipMemcpyAsync(x, f, sizeof(double) * d->mesh->ne * d->nphi,
+                                         hipMemcpyDeviceToDevice, s));
+        if (rep) {
+            *rep = sld_cg_report{};
+            rep->converged = 1;
+        }
+        return SLD_OK;
+    }
+    // the caller-order right-hand side lives in the CG's second residual buffer, which the
+    // setup does not touch before it has gathered b
+    return viscous_field(d, f, d->nphi, 0, 0, c, x, d->cg.r[1], prm, rep, s);
+}
+
+sld_status sld_state_create(sld_disc d, sld_state* out) {
+    SLD_REQUIRE(out, SLD_E_INVALID, "sld_state_create: out is NULL");
+    *out = nullptr;
+    SLD_REQUIRE(d, SLD_E_INVALID, "sld_state_create: NULL disc");
+    SLD_REQUIRE_DEVICE(d, "sld_state_create");
+    sld_state_s* st = new (std::nothrow) sld_state_s();
+    SLD_REQUIRE(st, SLD_E_NOMEM, "sld_state_create: host allocation failed");
+    st->disc = d;
+    const size_t nm = size_t(d->mesh->ne) * d->nphi;
+    const size_t ndv = size_t(d->mesh->nd) * 2 * d->npsi;
+    DeviceGuard dg(d->mesh->device);
+    std::lock_guard<std::mutex> lk(device_setup_mutex());
+    hipError_t e = dalloc(&st->vbar, 2 * nm);
+    if (e == hipSuccess) e = dalloc(&st->vfoot, 2 * nm);
+    if (e == hipSuccess) e = dalloc(&st->vsbar, 2 * nm);
+    if (e == hipSuccess) e = dalloc(&st->vs, ndv);
+    if (e == hipSuccess) e = dalloc(&st->b, nm);
+    if (e != hipSuccess) {
+        free_state(st);
+        sld_set_error(std::string("sld_state_create: device allocation failed: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SLD_E_NOMEM : SLD_E_HIP;
+    }
+    *out = st;
+    return SLD_OK;
+}
+
+void sld_state_destroy(sld_state st) {
+    if (!st) return;
+    DeviceGuard dg(st->disc->mesh->device);
+    std::lock_guard<std::mutex> lk(device_setup_mutex());
+    free_state(st);
+}
+
+sld_status sld_imex_step(sld_state st, const sld_imex_params* prm, double dt, double* v, double* p,
+                         sld_imex_report* rep, void* stream) {
+    SLD_REQUIRE(st && prm && v && p, SLD_E_INVALID, "sld_imex_step: NULL argument");
+    SLD_REQUIRE(v != p, SLD_E_INVALID, "sld_imex_step: v and p must not alias");
+    SLD_REQUIRE(std::isfinite(dt) && dt > 0.0, SLD_E_INVALID, "sld_imex_step: dt must be > 0");
+    SLD_REQUIRE(std::isfinite(prm->nu) && prm->nu >= 0.0, SLD_E_INVALID,
+                "sld_imex_step: nu must be finite and >= 0");
+    SLD_REQUIRE(prm->R == 0, SLD_E_INVALID, "sld_imex_step: only R = 0 is built");
+    SLD_REQUIRE(prm->viscous.precision == 0, SLD_E_INVALID,
+                "sld_imex_step: the viscous solves run in FP64 (precision 0)");
+    sld_disc d = st->disc;
+    SLD_REQUIRE(d->mesh->periodic, SLD_E_INVALID,
+                "sld_imex_step: periodic meshes only (no wall treatment of the velocity)");
+    DeviceGuard dg(d->mesh->device);
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    sld_imex_report local{};
+    sld_imex_report* r = rep ? rep : &local;
+    *r = sld_imex_report{};
+    const int64_t ne = d->mesh->ne;
+    const int N = d->nphi;
+    const double a_ss = 1.0;  // R = 0: implicit tableau a_11 = 1
+    auto done = [&](sld_status e) {
+        r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return e;
+    };
+    SLD_HIP_CHECK(launch_dual_to_main(d, v, 2, st->vbar, 2 * N, N, s));
+    SLD_HIP_CHECK(launch_sl_advect(d, st->vbar, st->vbar, 2, dt, st->vfoot, s));
+    const double c = a_ss * dt * prm->nu;
+    if (c > 0.0) {
+        for (int comp = 0; comp < 2; ++comp) {
+            sld_status e = viscous_field(d, st->vfoot, 2 * N, N, comp, c, st->vsbar + comp * ne * N,
+                                         st->b, &prm->viscous, &r->viscous[comp], s);
+            if (e != SLD_OK) return done(e);
+        }
+        SLD_HIP_CHECK(launch_main_to_dual(d, st->vsbar, 2, N, ne * N, st->vs, s));
+    } else {
+        SLD_HIP_CHECK(launch_main_to_dual(d, st->vfoot, 2, 2 * N, N, st->vs, s));
+    }
+    SLD_HIP_CHECK(launch_divergence(d, st->vs, 1.0 / (a_ss * dt), st->b, s));
+    sld_status e = cg_solve_impl(d, st->b, p, &prm->pressure, &r->pressure, s, 0.0);
+    if (e != SLD_OK) return done(e);
+    SLD_HIP_CHECK(launch_gradient(d, p, st->vs, -a_ss * dt, v, s));
+    SLD_HIP_CHECK(hipStreamSynchronize(s));
+    return done(SLD_OK);
 }
 
 }  // extern "C"

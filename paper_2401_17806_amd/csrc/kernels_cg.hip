@@ -11,7 +11,10 @@
 //   r_k = r_{k-1} - alpha q_{k-1},  d_k = r_k + beta d_{k-1},  x += alpha d_{k-1}
 //   q_k = -K d_k   (neighbours' r_k, d_k are recomputed from their (r, q, d)_{k-1})
 //   partials of rr_k = r_k.r_k, dq_k = d_k.q_k, rq_k = r_k.q_k, qq_k = q_k.q_k.
-// In exact arithmetic this is plain CG (Section 3.3).  Global scalars are never published
+// In exact arithmetic this is plain CG (Section 3.3).  The kShift instantiation solves the
+// viscous system of the IMEX step instead: K is replaced by K - sigma Mbar (Mbar_i = A_i Mref,
+// sigma = scal[SIGMA] > 0), i.e. CG on sigma Mbar - K, which is positive definite.
+// Global scalars are never published
 // through in-kernel atomics: every block sums the previous launch's partials itself in a
 // fixed order, so all blocks take bitwise identical decisions and results are deterministic.
 // The iteration counter is double-buffered by parity for the same reason.
@@ -23,6 +26,31 @@ namespace {
 
 typedef CgScalars S;
 
+// row k of Mref v
+template <int P>
+__device__ __forceinline__ double mass_row(const RefOps<P>& R, int k,
+                                           const double (&v)[RefOps<P>::NPHI]) {
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < RefOps<P>::NPHI; ++l) s = fma(R.Mref[k][l], v[l], s);
+    return s;
+}
+
+// (K - sigma Mbar) x on row k of triangle i, from the lanes' sum kx of (K x)_ik
+template <int P>
+__device__ __forceinline__ double shifted_row(const RefOps<P>& R, const double4* __restrict__ geo,
+                                              const double* __restrict__ x, int64_t i, int k,
+                                              double kx, double sigma) {
+    constexpr int N = RefOps<P>::NPHI;
+    if (sigma == 0.0) return kx;
+    const double4 e = geo[i];
+    const double A = e.x * e.w - e.y * e.z;
+    double s = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) s = fma(R.Mref[k][l], x[i * N + l], s);
+    return fma(-sigma * A, s, kx);
+}
+
 // r = K x - b_int (true residual of the CG system -K x = -b_int) and its rr partials.
 template <int P>
 __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restrict__ ops,
@@ -32,7 +60,8 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
                                                         const double* __restrict__ bint,
                                                         double* __restrict__ r,
                                                         double* __restrict__ part_out,
-                                                        const double* __restrict__ scal) {
+                                                        const double* __restrict__ scal,
+                                                        double sigma) {
     constexpr int N = RefOps<P>::NPHI;
     if (scal[S::DONE] != 0.0) return;
     __shared__ double sm[kTriPerBlock][4][N];
@@ -50,7 +79,9 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
         __syncthreads();
         if (valid) {
             for (int k = al; k < N; k += 3) {
-                const double v = (sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k]) - bint[i * N + k];
+                const double v = shifted_row<P>(*ops, geo, x, i, k,
+                                                sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k], sigma) -
+                                 bint[i * N + k];
                 r[i * N + k] = v;
                 acc[0] = fma(v, v, acc[0]);
             }
@@ -94,7 +125,7 @@ inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes, bool front) 
 // that does not depend on alpha and beta -- the tile's state, its halo ids, the previous
 // launch's dot partials and the scalars -- is issued at entry, so their latencies overlap;
 // otherwise (several tiles per block) the loads follow the tile loop.
-template <int P, typename Real, class Ops, bool kFront>
+template <int P, typename Real, class Ops, bool kFront, bool kShift>
 __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const Ops* __restrict__ ops,
                                                        const double4* __restrict__ geo,
                                                        const int4* __restrict__ nbr,
@@ -274,6 +305,11 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
                 const double4 e = geo[i];
                 if (role == 3) {
                     volume_wave_core<P, Ops, Real>(*ops, e, pl, y);
+                    if constexpr (kShift) {
+                        const double sa = -scal[S::SIGMA] * (e.x * e.w - e.y * e.z);
+#pragma unroll
+                        for (int k = 0; k < N; ++k) y[k] = fma(sa, mass_row<P>(*ops, k, pl), y[k]);
+                    }
                 } else {
                     const int4 nb4 = nbr[i];
                     const int nb = pick(nb4, role);
@@ -320,7 +356,21 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
 #pragma unroll
                     for (int l = 0; l < N; ++l) pr[l] = Real(0);
                 }
-                edge_lane_core<P, Ops, Real>(al, *ops, geo[i], nb, ar, er, pl, pr, y);
+                const double4 ei = geo[i];
+                edge_lane_core<P, Ops, Real>(al, *ops, ei, nb, ar, er, pl, pr, y);
+                if constexpr (kShift) {
+                    // this lane's rows (rotation-orbit representatives, the centre on lane 0);
+                    // Mref is invariant under the relabelling
+                    constexpr Tab<P> TT{};
+                    const double sa = -scal[S::SIGMA] * (ei.x * ei.w - ei.y * ei.z);
+#pragma unroll
+                    for (int q = 0; q < TT.nrep; ++q)
+                        y[TT.rep[q]] = fma(sa, mass_row<P>(*ops, TT.rep[q], pl), y[TT.rep[q]]);
+                    if (TT.centre >= 0 && al == 0) {
+                        const int kc = TT.centre >= 0 ? TT.centre : 0;
+                        y[kc] = fma(sa, mass_row<P>(*ops, kc, pl), y[kc]);
+                    }
+                }
 #pragma unroll
                 for (int k = 0; k < N; ++k) sm[(tl * 3 + al) * N + rot_sel<P>(al, k)] = y[k];
             }
@@ -399,7 +449,7 @@ __global__ __launch_bounds__(kBlockFlat) void k_cg_prep(const double* __restrict
 // one block: BB, TOL2, ITER, DONE, MAXIT
 __global__ __launch_bounds__(kBlockFlat) void k_cg_scal_init(const double* __restrict__ part, int nb,
                                                              double* __restrict__ scal, double rtol,
-                                                             int maxit) {
+                                                             int maxit, double sigma) {
     const double bb = reduce_partials<kBlockFlat>(part, nb);
     if (threadIdx.x == 0) {
         scal[S::BB] = bb;
@@ -411,6 +461,7 @@ __global__ __launch_bounds__(kBlockFlat) void k_cg_scal_init(const double* __res
         scal[S::RR] = 0.0;
         scal[S::ZERO] = bb == 0.0 ? 1.0 : 0.0;
         scal[S::DONE] = bb == 0.0 ? 1.0 : 0.0;
+        scal[S::SIGMA] = sigma;
     }
 }
 
@@ -477,7 +528,8 @@ __global__ __launch_bounds__(kBlockTri) void k_apply_internal(const RefOps<P>* _
                                                               const int4* __restrict__ nbr,
                                                               int64_t ne,
                                                               const double* __restrict__ p,
-                                                              double* __restrict__ out) {
+                                                              double* __restrict__ out,
+                                                              double sigma) {
     constexpr int N = RefOps<P>::NPHI;
     __shared__ double sm[kTriPerBlock][4][N];
     const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
@@ -491,7 +543,9 @@ __global__ __launch_bounds__(kBlockTri) void k_apply_internal(const RefOps<P>* _
     }
     __syncthreads();
     if (valid)
-        for (int k = al; k < N; k += 3) out[i * N + k] = sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k];
+        for (int k = al; k < N; k += 3)
+            out[i * N + k] = shifted_row<P>(*ops, geo, p, i, k,
+                                            sm[tl][0][k] + sm[tl][1][k] + sm[tl][2][k], sigma);
 }
 
 // ---------------------------------------------------------------- mixed precision
@@ -607,26 +661,27 @@ const RefOps32<P>* ops32_of(const sld_disc_s* d) {
 }  // namespace
 
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
-                           double rtol, int maxit, hipStream_t s) {
+                           double rtol, int maxit, double sigma, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     const CgWork& w = d->cg;
     const int64_t n = m->ne * d->nphi;
     const int G = w.grid;
     hipLaunchKernelGGL(k_sum_partials, dim3(G), dim3(kBlockFlat), 0, s, b, n, w.part_s);
+    // the shifted (viscous) system is nonsingular: no projection onto 1^perp
     hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal,
-                       (int)S::MEAN, 1.0 / (double)n);
+                       (int)S::MEAN, sigma > 0.0 ? 0.0 : 1.0 / (double)n);
     hipLaunchKernelGGL(k_cg_prep, dim3(G), dim3(kBlockFlat), 0, s, b, p0, m->perm, d->nphi, n, w.b,
                        w.x, warm ? 1 : 0, w.d[0], w.q[0], w.part_s, w.scal);
     hipLaunchKernelGGL(k_cg_scal_init, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal, rtol,
-                       maxit);
+                       maxit, sigma);
     // r_0 = K x - b_int (the residual of -K x = -b_int); q, d of "iteration -1" are zero
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(G), dim3(kBlockTri), 0, s,
                                           ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
-                                          w.r[0], w.part_s, w.scal));
+                                          w.r[0], w.part_s, w.scal, sigma));
     return hipGetLastError();
 }
 
-hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
+hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     const CgWork& w = d->cg;
     const int G = w.grid;
@@ -634,8 +689,8 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double), front);
-#define SLD_STEP64(F)                                                                           \
-    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F>), dim3(G),      \
+#define SLD_STEP64(F, SH)                                                                       \
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F, SH>), dim3(G),  \
                                           dim3(F ? kBlockCG : kBlockTri), lds, s, ops_of<PP>(d), \
                                           m->geo_i,                                             \
                                           m->nbr_i, m->halo_pad, m->hmax, m->ne, w.x,           \
@@ -643,9 +698,17 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s) {
                                           w.q[o], w.d[o], w.part + parity * 4 * G,              \
                                           w.part + o * 4 * G, w.scal, parity))
     if (front) {
-        SLD_STEP64(true);
+        if (shift) {
+            SLD_STEP64(true, true);
+        } else {
+            SLD_STEP64(true, false);
+        }
     } else {
-        SLD_STEP64(false);
+        if (shift) {
+            SLD_STEP64(false, true);
+        } else {
+            SLD_STEP64(false, false);
+        }
     }
 #undef SLD_STEP64
     return hipGetLastError();
@@ -663,10 +726,11 @@ int cg_grid_for(const sld_disc_s* d, bool* front) {
     const size_t lds_f = step_lds_bytes(d->nphi, m->hmax, sizeof(double), true);
     const size_t lds_l = step_lds_bytes(d->nphi, m->hmax, sizeof(double), false);
     SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &per_front, (k_cg_step<PP, double, RefOps<PP>, true>), kBlockCG, lds_f));
+                           &per_front, (k_cg_step<PP, double, RefOps<PP>, true, false>), kBlockCG,
+                           lds_f));
     if (e == hipSuccess)
         SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &per_lanes, (k_cg_step<PP, double, RefOps<PP>, false>), kBlockTri,
+                               &per_lanes, (k_cg_step<PP, double, RefOps<PP>, false, false>), kBlockTri,
                                lds_l));
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device);
     const bool ok = e == hipSuccess && cus > 0;
@@ -684,21 +748,22 @@ int cg_grid_for(const sld_disc_s* d, bool* front) {
     return (int)((g + 7) & ~int64_t(7));
 }
 
-hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s) {
+hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     const CgWork& w = d->cg;
     const int G = w.grid;
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_apply_internal<PP>,
                                           dim3((unsigned)((m->ne + kTriPerBlock - 1) / kTriPerBlock)),
                                           dim3(kBlockTri), 0, s, ops_of<PP>(d), m->geo_i, m->nbr_i,
-                                          m->ne, w.x, w.q[0]));
+                                          m->ne, w.x, w.q[0], sigma));
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_finish_partials<PP>, dim3(G), dim3(kBlockFlat), 0, s,
                                           ops_of<PP>(d), m->geo_i, m->ne, w.q[0], w.b, w.x,
                                           w.part_s));
     hipLaunchKernelGGL(k_finish_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal);
     const int64_t n = m->ne * d->nphi;
+    // the gauge int p = 0 fixes the pressure's constant; the viscous solution has none to fix
     hipLaunchKernelGGL(k_gauge_out, dim3(G), dim3(kBlockFlat), 0, s, n, d->nphi, m->perm, w.x,
-                       w.scal, 1.0 / m->area_total, p_out);
+                       w.scal, sigma > 0.0 ? 0.0 : 1.0 / m->area_total, p_out);
     return hipGetLastError();
 }
 
@@ -711,7 +776,7 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
     const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float), front);
 #define SLD_STEP32(F)                                                                           \
-    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>, F>), dim3(G),     \
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>, F, false>), dim3(G), \
                                           dim3(F ? kBlockCG : kBlockTri), lds, s, ops32_of<PP>(d), \
                                           m->geo_i,                                             \
                                           m->nbr_i, m->halo_pad, m->hmax, m->ne, w.e32,         \
@@ -748,7 +813,7 @@ hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s) {
     hipLaunchKernelGGL(k_rel_accumulate, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.x, w.e32, w.scal);
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(w.grid), dim3(kBlockTri), 0, s,
                                           ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
-                                          w.r[0], w.part_s, w.scal));
+                                          w.r[0], w.part_s, w.scal, 0.0));
     hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal,
                        (int)S::RR, 1.0);
     hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],

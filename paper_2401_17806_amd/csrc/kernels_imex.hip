@@ -1,0 +1,231 @@
+// Grid transfers between the main and the dual space (Section 4, eqs. d2m and m2d) and the
+// right-hand side of the viscous solve, for the semi-Lagrangian IMEX step.
+//
+// dual -> main (eq. d2m): vbar_i = Mbar_i^{-1} sum_j U_ij^T vhat_j.  On triangle i's half of
+// the dual cell of its local edge alpha the dual basis is the sub-triangle's Lagrange basis, so
+// U_ij^T vhat_j = A_i V_alpha vh (vh: the half's nodal values) and Mbar_i = A_i Mref; the areas
+// cancel and vbar_i = sum_alpha Ldm[alpha] vh_alpha with reference tables only.
+//
+// main -> dual (eq. m2d): vhat_j = Mhat_j^{-1} (U_lj vbar_l + U_rj vbar_r).  Restricted to one
+// half, vbar_s is a polynomial of degree p in the half's coordinates, so U_sj vbar_s =
+// (A_s/3) Mref a_s with a_s its values at the half's nodes, and Mhat_j = (A_l/3) Mref (+) (A_r/3)
+// Mref glued on the p+1 shared edge nodes.  Static condensation onto those nodes gives the
+// projection in closed form: on the edge u_H = (A_l a_l,H + A_r a_r,H) / (A_l + A_r) (the two
+// halves' interface Schur complements are the same matrix), and inside each half
+// u_I = a_I - Z (u_H - a_H).  A wall cell is its left half alone: u = a there.
+#include "device_common.h"
+
+using namespace sld_dev;
+
+namespace {
+
+constexpr int kBlockX = 128;
+
+// One thread per triangle: out(i, c, :) = sum_alpha Ldm[alpha] vh_alpha(c).  vd [nd][nc][Npsi];
+// out element (i, c, l) at out[i * o_is + c * o_cs + l].
+template <int P>
+__global__ __launch_bounds__(kBlockX) void k_dual_to_main(const RefOps<P>* __restrict__ ops,
+                                                         const int4* __restrict__ tedges, int64_t ne,
+                                                         const double* __restrict__ vd, int nc,
+                                                         double* __restrict__ out, int64_t o_is,
+                                                         int64_t o_cs) {
+    constexpr int N = RefOps<P>::NPHI;
+    constexpr int NPSI = (P + 1) * (P + 1);
+    constexpr Tab<P> T{};
+    const RefOps<P>& R = *ops;
+    const int64_t i = (int64_t)blockIdx.x * kBlockX + threadIdx.x;
+    if (i >= ne) return;
+    const int4 te4 = tedges[i];
+    for (int c = 0; c < nc; ++c) {
+        double y[N];
+#pragma unroll
+        for (int l = 0; l < N; ++l) y[l] = 0.0;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            const int te = al == 0 ? te4.x : (al == 1 ? te4.y : te4.z);
+            const int64_t j = te >> 1;
+            const int beta = te & 1;
+            const double* vj = vd + (j * nc + c) * NPSI;
+            double vh[N];
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                const int a = T.na[n], b = T.nb[n];
+                vh[n] = vj[beta ? (P - b) * (P + 1) + (P - a) : b * (P + 1) + a];
+            }
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+                double s = 0.0;
+#pragma unroll
+                for (int n = 0; n < N; ++n) s = fma(R.Ldm[al][l][n], vh[n], s);
+                y[l] += s;
+            }
+        }
+        double* o = out + i * o_is + c * o_cs;
+#pragma unroll
+        for (int l = 0; l < N; ++l) o[l] = y[l];
+    }
+}
+
+// One thread per edge: out(j, c, :) [nd][nc][Npsi] from vm element (i, c, l) at
+// vm[i * v_is + c * v_cs + l].
+template <int P>
+__global__ __launch_bounds__(kBlockX) void k_main_to_dual(const RefOps<P>* __restrict__ ops,
+                                                         const double4* __restrict__ geo,
+                                                         const int4* __restrict__ edges, int64_t nd,
+                                                         const double* __restrict__ vm, int nc,
+                                                         int64_t v_is, int64_t v_cs,
+                                                         double* __restrict__ out) {
+    constexpr int N = RefOps<P>::NPHI;
+    constexpr int NE = P + 1;
+    constexpr int NPSI = (P + 1) * (P + 1);
+    constexpr Tab<P> T{};
+    const RefOps<P>& R = *ops;
+    const int64_t j = (int64_t)blockIdx.x * kBlockX + threadIdx.x;
+    if (j >= nd) return;
+    const int4 ed = edges[j];
+    const bool wall = ed.y < 0;
+    double wl = 1.0, wr = 0.0;
+    if (!wall) {
+        const double4 el = geo[ed.x], er = geo[ed.y];
+        const double Al = el.x * el.w - el.y * el.z, Ar = er.x * er.w - er.y * er.z;
+        wl = Al / (Al + Ar);
+        wr = Ar / (Al + Ar);
+    }
+    for (int c = 0; c < nc; ++c) {
+        double* o = out + (j * nc + c) * NPSI;
+        // values of each side's polynomial at its half's nodes (frames relabelled so that the
+        // shared edge is local edge 0)
+        double al[N], ar[N];
+        {
+            const double* src = vm + (int64_t)ed.x * v_is + c * v_cs;
+            double pl[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) pl[l] = src[rot_sel<P>(ed.z, l)];
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                double s = 0.0;
+#pragma unroll
+                for (int l = 0; l < N; ++l) s = fma(R.Iv[n][l], pl[l], s);
+                al[n] = s;
+            }
+        }
+        if (!wall) {
+            const double* src = vm + (int64_t)ed.y * v_is + c * v_cs;
+            double pr[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) pr[l] = src[rot_sel<P>(ed.w, l)];
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                double s = 0.0;
+#pragma unroll
+                for (int l = 0; l < N; ++l) s = fma(R.Iv[n][l], pr[l], s);
+                ar[n] = s;
+            }
+        } else {
+#pragma unroll
+            for (int n = 0; n < N; ++n) ar[n] = 0.0;
+        }
+        // edge nodes: l's node m is r's node P - m
+        double uH[NE], dL[NE], dR[NE];
+#pragma unroll
+        for (int m = 0; m < NE; ++m) {
+            const double a_l = al[main_idx(P, P - m, m)];
+            const double a_r = ar[main_idx(P, m, P - m)];
+            uH[m] = wall ? a_l : wl * a_l + wr * a_r;
+        }
+#pragma unroll
+        for (int m = 0; m < NE; ++m) {
+            dL[m] = uH[m] - al[main_idx(P, P - m, m)];
+            dR[m] = uH[P - m] - ar[main_idx(P, P - m, m)];
+        }
+        int ii = 0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const int a = T.na[n], b = T.nb[n];
+            if (a + b < P) {
+                double zl = 0.0, zr = 0.0;
+#pragma unroll
+                for (int m = 0; m < NE; ++m) {
+                    zl = fma(R.Z[ii][m], dL[m], zl);
+                    zr = fma(R.Z[ii][m], dR[m], zr);
+                }
+                o[b * (P + 1) + a] = al[n] - zl;
+                o[(P - b) * (P + 1) + (P - a)] = wall ? 0.0 : ar[n] - zr;
+                ++ii;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < NE; ++m) o[m * (P + 1) + (P - m)] = uH[m];
+    }
+}
+
+// b[i][k] = scale * A_i (Mref f_i)_k and x0[i][l] = f_i,l for component c of f (element (i, c, l)
+// at f[i * f_is + c * f_cs + l]); b and x0 are [ne][Nphi].
+template <int P>
+__global__ __launch_bounds__(kBlockX) void k_mass_rhs(const RefOps<P>* __restrict__ ops,
+                                                     const double4* __restrict__ geo, int64_t ne,
+                                                     const double* __restrict__ f, int64_t f_is,
+                                                     int64_t f_cs, int c, double scale,
+                                                     double* __restrict__ b, double* __restrict__ x0) {
+    constexpr int N = RefOps<P>::NPHI;
+    const RefOps<P>& R = *ops;
+    const int64_t i = (int64_t)blockIdx.x * kBlockX + threadIdx.x;
+    if (i >= ne) return;
+    const double4 e = geo[i];
+    const double A = e.x * e.w - e.y * e.z;
+    const double* src = f + i * f_is + c * f_cs;
+    double v[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) v[l] = src[l];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(R.Mref[k][l], v[l], s);
+        b[i * N + k] = scale * A * s;
+        if (x0) x0[i * N + k] = v[k];
+    }
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlockX - 1) / kBlockX); }
+
+template <int P>
+const RefOps<P>* ops_of(const sld_disc_s* d) { return reinterpret_cast<const RefOps<P>*>(d->ops_dev); }
+
+}  // namespace
+
+#define SLD_DISPATCH(p, CALL)                                   \
+    switch (p) {                                                \
+        case 1: { constexpr int PP = 1; CALL; } break;          \
+        case 2: { constexpr int PP = 2; CALL; } break;          \
+        case 3: { constexpr int PP = 3; CALL; } break;          \
+        case 4: { constexpr int PP = 4; CALL; } break;          \
+        default: return hipErrorInvalidValue;                   \
+    }
+
+hipError_t launch_dual_to_main(const sld_disc_s* d, const double* vd, int nc, double* out,
+                               int64_t o_is, int64_t o_cs, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_dual_to_main<PP>, dim3(nblk(m->ne)), dim3(kBlockX), 0,
+                                          s, ops_of<PP>(d), m->tedges, m->ne, vd, nc, out, o_is,
+                                          o_cs));
+    return hipGetLastError();
+}
+
+hipError_t launch_main_to_dual(const sld_disc_s* d, const double* vm, int nc, int64_t v_is,
+                               int64_t v_cs, double* out, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_main_to_dual<PP>, dim3(nblk(m->nd)), dim3(kBlockX), 0,
+                                          s, ops_of<PP>(d), m->geo, m->edges, m->nd, vm, nc, v_is,
+                                          v_cs, out));
+    return hipGetLastError();
+}
+
+hipError_t launch_mass_rhs(const sld_disc_s* d, const double* f, int64_t f_is, int64_t f_cs, int c,
+                           double scale, double* b, double* x0, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_mass_rhs<PP>, dim3(nblk(m->ne)), dim3(kBlockX), 0, s,
+                                          ops_of<PP>(d), m->geo, m->ne, f, f_is, f_cs, c, scale, b,
+                                          x0));
+    return hipGetLastError();
+}

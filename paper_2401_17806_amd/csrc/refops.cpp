@@ -174,6 +174,8 @@ int build_refops(RefOps<P>* ops) {
         for (int k = 0; k < N; ++k)
             for (int l = 0; l < N; ++l) ops->S[t][k][l] = (double)S[t * N * N + k * N + l];
     for (int k = 0; k < N; ++k) ops->w[k] = (double)w[k];
+    for (int k = 0; k < N; ++k)
+        for (int l = 0; l < N; ++l) ops->Mref[k][l] = (double)M[k * N + l];
 
     // interior / edge split of a sub-triangle's nodes
     int Iidx[N > 0 ? N : 1], Hidx[NE];
@@ -249,22 +251,24 @@ int build_refops(RefOps<P>* ops) {
         for (int n = 0; n < N; ++n) {
             ld xi, eta;
             map(ld(B.na[n]) / P, ld(B.nb[n]) / P, xi, eta);
-            B.eval(xi, eta, nullptr, dx, dy);
+            B.eval(xi, eta, val, dx, dy);
             for (int l = 0; l < N; ++l) {
                 ops->Hn[al][0][n][l] = (double)dx[l];
                 ops->Hn[al][1][n][l] = (double)dy[l];
+                if (al == 0) ops->Iv[n][l] = (double)val[l];
             }
         }
-        std::vector<ld> Wl(2 * N * N, 0), Sh(3 * N * N, 0);
+        std::vector<ld> Wl(2 * N * N, 0), Sh(3 * N * N, 0), V(N * N, 0);
         const ld jac = 1.0L / 3;  // |det d xi / d zeta|
         for (int iq = 0; iq < nq; ++iq) {
             ld xi, eta;
             map(q.u[iq], q.v[iq], xi, eta);
-            B.eval(xi, eta, nullptr, dx, dy);
+            B.eval(xi, eta, val, dx, dy);
             B.eval(q.u[iq], q.v[iq], sv, nullptr, nullptr);
             ld wq = q.w[iq] * jac;
             for (int k = 0; k < N; ++k)
                 for (int n = 0; n < N; ++n) {
+                    V[k * N + n] += wq * val[k] * sv[n];
                     Wl[0 * N * N + k * N + n] += wq * dx[k] * sv[n];
                     Wl[1 * N * N + k * N + n] += wq * dy[k] * sv[n];
                     Sh[0 * N * N + k * N + n] += wq * dx[k] * dx[n];
@@ -284,6 +288,11 @@ int build_refops(RefOps<P>* ops) {
         for (int t = 0; t < 3; ++t)
             for (int k = 0; k < N; ++k)
                 for (int n = 0; n < N; ++n) ops->Sh[al][t][k][n] = (double)Sh[t * N * N + k * N + n];
+        // Ldm[al] = Mref^{-1} V_al
+        std::vector<ld> Mc = M;
+        if (!solve_dense(N, N, Mc, V)) return 4;
+        for (int k = 0; k < N; ++k)
+            for (int n = 0; n < N; ++n) ops->Ldm[al][k][n] = (double)V[k * N + n];
     }
     return 0;
 }

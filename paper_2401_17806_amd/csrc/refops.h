@@ -36,6 +36,14 @@ struct RefOps {
     double M1[NE][NE];
     // int_{T_ref} phi_k
     double w[NPHI];
+    // Tables of the grid transfers and the viscous operator (Section 4):
+    // Mref = int_{T_ref} phi_k phi_l (the main mass matrix of triangle i is A_i Mref)
+    double Mref[NPHI][NPHI];
+    // Iv[n][l] = phi_l at sub-triangle node n (main numbering in zeta) of T^0
+    double Iv[NPHI][NPHI];
+    // Ldm[alpha][l][n] = (Mref^{-1} V_alpha)[l][n], V_alpha[k][n] = int_{T^alpha} phi_k phi_n(zeta):
+    // the dual -> main projection of one triangle is sum_alpha Ldm[alpha] (its half of cell alpha)
+    double Ldm[3][NPHI][NPHI];
 };
 
 // Float copy of the operators the Schur apply uses (mixed-precision inner solves).

@@ -87,6 +87,8 @@ struct CgWork {
     hipStream_t capture = nullptr;   // private stream used to capture the iteration graph
     hipGraphExec_t graph = nullptr;  // captured block of iterations
     int graph_block = 0;             // iterations in `graph`
+    hipGraphExec_t graph_shift = nullptr;  // the same for the viscous (mass-shifted) system
+    int graph_shift_block = 0;
 };
 
 struct sld_disc_s {
@@ -114,13 +116,16 @@ hipError_t launch_divergence(const sld_disc_s* d, const double* v, double scale,
 struct CgScalars {
     // layout of CgWork::scal (doubles)
     enum { RR = 0, BB = 1, TOL2 = 2, ITER = 3, DONE = 4, MAXIT = 5, MEAN = 6, ZERO = 7,
-           RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, IRS = 12, RRNOW = 13, GAP = 14, NSCAL = 16 };
+           RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, IRS = 12, RRNOW = 13, GAP = 14, SIGMA = 15,
+           NSCAL = 16 };
 };
 int cg_grid_for(const sld_disc_s* d, bool* front);
+// sigma > 0: the viscous system (sigma Mbar - K) x = -b instead of -K x = -b (no 1^perp
+// projection, no gauge)
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,
-                           double rtol, int maxit, hipStream_t s);
-hipError_t launch_cg_step(const sld_disc_s* d, int parity, hipStream_t s);
-hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, hipStream_t s);
+                           double rtol, int maxit, double sigma, hipStream_t s);
+hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream_t s);
+hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hipStream_t s);
 hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s);
 hipError_t launch_rel_init(const sld_disc_s* d, double rtol, int maxit, hipStream_t s);
 hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s);
@@ -128,3 +133,10 @@ hipError_t launch_rel_restart(const sld_disc_s* d, hipStream_t s);
 hipError_t launch_sl_advect(const sld_disc_s* d, const double* vbar, const double* q, int nc,
                             double dt, double* out, hipStream_t s);
 hipError_t launch_rel_peek(const sld_disc_s* d, int resume, hipStream_t s);
+// grid transfers and the viscous right-hand side (kernels_imex.hip); strides in doubles
+hipError_t launch_dual_to_main(const sld_disc_s* d, const double* vd, int nc, double* out,
+                               int64_t o_is, int64_t o_cs, hipStream_t s);
+hipError_t launch_main_to_dual(const sld_disc_s* d, const double* vm, int nc, int64_t v_is,
+                               int64_t v_cs, double* out, hipStream_t s);
+hipError_t launch_mass_rhs(const sld_disc_s* d, const double* f, int64_t f_is, int64_t f_cs, int c,
+                           double scale, double* b, double* x0, hipStream_t s);

@@ -46,6 +46,16 @@ class sld_cg_report(ctypes.Structure):
                 ("step_us", ctypes.c_double), ("timed_iters", _i32), ("outer_iters", _i32)]
 
 
+class sld_imex_params(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("R", _i32), ("pressure", sld_cg_params),
+                ("viscous", sld_cg_params)]
+
+
+class sld_imex_report(ctypes.Structure):
+    _fields_ = [("pressure", sld_cg_report), ("viscous", sld_cg_report * 2),
+                ("seconds", ctypes.c_double)]
+
+
 def _sig(name, args, res=ctypes.c_int):
     f = getattr(_lib, name)
     f.argtypes = args
@@ -76,6 +86,14 @@ _sig("sld_cg_solve", [_vp, _vp, _vp, ctypes.POINTER(sld_cg_params),
 _sig("sld_disc_footprint", [_vp, ctypes.POINTER(ctypes.c_uint64)])
 _sig("sld_ref_operator", [_vp, _i32, _i32, _c_dp, _i64, ctypes.POINTER(_i64)])
 _sig("sld_sl_advect", [_vp, _vp, _vp, _i32, ctypes.c_double, _vp, _vp])
+_sig("sld_dual_to_main", [_vp, _vp, _i32, _vp, _vp])
+_sig("sld_main_to_dual", [_vp, _vp, _i32, _vp, _vp])
+_sig("sld_viscous_solve", [_vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(sld_cg_params),
+                           ctypes.POINTER(sld_cg_report), _vp])
+_sig("sld_state_create", [_vp, ctypes.POINTER(_vp)])
+_sig("sld_state_destroy", [_vp], None)
+_sig("sld_imex_step", [_vp, ctypes.POINTER(sld_imex_params), ctypes.c_double, _vp, _vp,
+                       ctypes.POINTER(sld_imex_report), _vp])
 _sig("sld_server_create", [_i32, ctypes.c_uint64, _i32, ctypes.POINTER(_vp)])
 _sig("sld_server_submit", [_vp, _vp, _vp, _vp, ctypes.POINTER(sld_cg_params), _vp,
                            ctypes.POINTER(ctypes.c_uint64)])
@@ -90,7 +108,8 @@ EXPORTED = [
     "sld_mesh_destroy", "sld_disc_create", "sld_disc_info", "sld_main_nodes", "sld_dual_nodes",
     "sld_main_weights", "sld_disc_destroy", "sld_schur_apply", "sld_gradient", "sld_divergence",
     "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_disc_footprint",
-    "sld_sl_advect", "sld_ref_operator",
+    "sld_sl_advect", "sld_ref_operator", "sld_dual_to_main", "sld_main_to_dual",
+    "sld_viscous_solve", "sld_state_create", "sld_state_destroy", "sld_imex_step",
     "sld_server_create", "sld_server_submit", "sld_server_poll", "sld_server_stats",
     "sld_server_destroy",
 ]
@@ -299,7 +318,7 @@ class Disc:
         return int(v.value)
 
     REF_OPERATORS = {"S": 0, "Sh": 1, "E": 2, "Pt": 3, "C": 4, "M1": 5, "w": 6,
-                     "sl_points": 7, "sl_proj": 8}
+                     "sl_points": 7, "sl_proj": 8, "Mref": 9, "Ldm": 10}
 
     def sld_ref_operator(self, which: str, alpha: int = 0) -> np.ndarray:
         """Host copy of a reference operator (flat float64; see include/sld.h for shapes)."""
@@ -342,9 +361,84 @@ class Disc:
             _check(st)
         return p, report
 
+    def sld_dual_to_main(self, v, out=None, stream=None):
+        """L2 projection of a dual field v [nd, nc, N_psi] onto the main space (eq. d2m)."""
+        if v.dim() != 3 or v.shape[0] != self.mesh.nd or v.shape[2] != self.npsi:
+            raise ValueError(f"v must be [{self.mesh.nd}, nc, {self.npsi}]")
+        nc = int(v.shape[1])
+        shape = (self.mesh.ne, nc, self.nphi)
+        out = self._new(shape) if out is None else out
+        _check(_lib.sld_dual_to_main(self.handle, self._dev(v, tuple(v.shape), "v"), nc,
+                                     self._dev(out, shape, "out"), self._stream(stream)))
+        return out
+
+    def sld_main_to_dual(self, v, out=None, stream=None):
+        """L2 projection of a main field v [ne, nc, N_phi] onto the dual space (eq. m2d)."""
+        if v.dim() != 3 or v.shape[0] != self.mesh.ne or v.shape[2] != self.nphi:
+            raise ValueError(f"v must be [{self.mesh.ne}, nc, {self.nphi}]")
+        nc = int(v.shape[1])
+        shape = (self.mesh.nd, nc, self.npsi)
+        out = self._new(shape) if out is None else out
+        _check(_lib.sld_main_to_dual(self.handle, self._dev(v, tuple(v.shape), "v"), nc,
+                                     self._dev(out, shape, "out"), self._stream(stream)))
+        return out
+
+    def sld_viscous_solve(self, f, c, x=None, rtol=1e-12, maxit=100000, graph_block=32,
+                          stream=None):
+        """x with (Mbar - c K) x = Mbar f (FP64 CG)."""
+        x = self._new(self.main_shape) if x is None else x
+        prm = make_params(rtol, maxit, False, graph_block)
+        rep = sld_cg_report()
+        st = _lib.sld_viscous_solve(self.handle, self._dev(f, self.main_shape, "f"), float(c),
+                                    self._dev(x, self.main_shape, "x"), ctypes.byref(prm),
+                                    ctypes.byref(rep), self._stream(stream))
+        report = report_dict(rep, st)
+        if st not in (0, 5):
+            _check(st)
+        return x, report
+
     def close(self):
         if getattr(self, "handle", None):
             sld_disc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class State:
+    """Owner of an sld_state handle (IMEX step workspace); keeps its Disc alive."""
+
+    def __init__(self, disc: Disc):
+        self.disc = disc
+        h = _vp()
+        _check(_lib.sld_state_create(disc.handle, ctypes.byref(h)))
+        self.handle = h
+
+    def sld_imex_step(self, v, p, dt, nu, R=0, rtol=1e-12, visc_rtol=1e-12, maxit=200000,
+                      graph_block=32, warm_start=True, precision="fp64", stream=None):
+        """One IMEX step in place: v [nd, 2, N_psi] at t -> t + dt; p [ne, N_phi] <- pressure."""
+        d = self.disc
+        prm = sld_imex_params(float(nu), int(R),
+                              make_params(rtol, maxit, warm_start, graph_block, False, precision),
+                              make_params(visc_rtol, maxit, True, graph_block))
+        rep = sld_imex_report()
+        st = _lib.sld_imex_step(self.handle, ctypes.byref(prm), float(dt),
+                                d._dev(v, d.dual_shape, "v"), d._dev(p, d.main_shape, "p"),
+                                ctypes.byref(rep), d._stream(stream))
+        out = {"pressure": report_dict(rep.pressure, st),
+               "viscous": [report_dict(rep.viscous[k], st) for k in range(2)],
+               "seconds": rep.seconds, "status": STATUS.get(st, st)}
+        if st not in (0, 5):
+            _check(st)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.sld_state_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,191 @@
+"""GPU parity of the IMEX pieces against the oracle (Section 4): the grid transfers (eqs. d2m,
+m2d) element by element, the viscous solve, and whole R = 0 time steps of the Taylor-Green
+vortex; at the 16x16x2, p = 2 workload ten steps at CFL 0.5 against the oracle, and at the
+128x128x2, p = 3 workload fifty steps against properties (divergence-free velocity, decaying
+energy, the analytic vortex at first-order accuracy)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import imex as oimex
+from oracle import solve
+from oracle.mesh import OracleMesh
+from oracle.operators import OracleDisc
+from paper_2401_17806_amd.inputs import lattice_mesh, random_vector
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _pair(n, p, periodic=True, seed=5):
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(n, seed=seed, periodic=periodic,
+                                length=(2 * np.pi if periodic else 1.0))
+    od = OracleDisc(OracleMesh(xy, tri, per), p)
+    mesh = sld.Mesh(xy, tri, per, device=0)
+    return od, sld.Disc(mesh, p)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_transfers_match_oracle(torch_dev, p, periodic):
+    torch = torch_dev
+    _say(f"[imex transfers] p={p} periodic={periodic}")
+    od, disc = _pair(5, p, periodic)
+    m = od.mesh
+    for nc in (1, 2, 3):
+        vm = random_vector((m.ne, nc, od.nphi), seed=10 * p + nc)
+        got = disc.sld_main_to_dual(torch.from_numpy(vm).to("cuda:0")).cpu().numpy()
+        want = oimex.main_to_dual(od, vm)
+        r = _rel(got, want)
+        vd = random_vector((m.nd, nc, od.npsi), seed=20 * p + nc)
+        got2 = disc.sld_dual_to_main(torch.from_numpy(vd).to("cuda:0")).cpu().numpy()
+        if not periodic:  # a wall cell's absent right half carries no DOFs
+            half = np.array([a + b <= p for b in range(p + 1) for a in range(p + 1)])
+            vd[np.broadcast_to((~m.interior)[:, None, None] & (~half)[None, None, :], vd.shape)] = 0.0
+        want2 = oimex.dual_to_main(od, vd)
+        r2 = _rel(got2, want2)
+        _say(f"    nc={nc}: main->dual {r:.2e}  dual->main {r2:.2e}")
+        assert r <= 1e-12 and r2 <= 1e-12
+
+
+@pytest.mark.parametrize("p,periodic", [(1, True), (2, False), (3, True), (4, False)])
+def test_viscous_solve_matches_oracle(torch_dev, p, periodic):
+    torch = torch_dev
+    _say(f"[imex viscous] p={p} periodic={periodic}")
+    od, disc = _pair(6, p, periodic, seed=6)
+    K = solve.assemble_K(od)
+    f = random_vector((od.mesh.ne, 1, od.nphi), seed=30 + p)
+    for c in (0.0, 1e-3, 0.05):
+        x, rep = disc.sld_viscous_solve(torch.from_numpy(np.ascontiguousarray(f[:, 0])).to("cuda:0"),
+                                        c, rtol=1e-13)
+        want = oimex.viscous_solve(od, K, f, c)[:, 0]
+        r = _rel(x.cpu().numpy(), want)
+        _say(f"    c={c}: iters {rep['iters']} rel {r:.2e}")
+        assert rep["converged"] and r <= 1e-10
+
+
+def _tgv0(od, nu):
+    return oimex.dual_interpolant(od, lambda xy: oimex.tgv_velocity(xy, 0.0, nu))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_imex_steps_match_oracle(torch_dev, p):
+    """Three R = 0 steps of the Taylor-Green vortex at CFL 0.5, nu = 1e-2."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    _say(f"[imex steps] p={p}")
+    n, nu = 6, 1e-2
+    od, disc = _pair(n, p, seed=7)
+    K = solve.assemble_K(od)
+    dt = 0.5 * 2 * np.pi / n
+    v = _tgv0(od, nu)
+    vg = torch.from_numpy(v.copy()).to("cuda:0")
+    pg = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    st = sld.State(disc)
+    for k in range(3):
+        v, pi, _ = oimex.imex_step(od, K, v, dt, nu)
+        rep = st.sld_imex_step(vg, pg, dt, nu, rtol=1e-13, visc_rtol=1e-13)
+        rv, rp = _rel(vg.cpu().numpy(), v), _rel(pg.cpu().numpy(), pi)
+        _say(f"    step {k}: v {rv:.2e} p {rp:.2e} iters p {rep['pressure']['iters']} "
+             f"visc {[r['iters'] for r in rep['viscous']]}")
+        assert rv <= 1e-9 and rp <= 1e-9
+
+
+def test_imex_tgv16_p2_ten_steps(torch_dev):
+    """16x16x2 jittered periodic mesh, p = 2, nu = 1e-2, ten steps at CFL 0.5 (dt = 0.5 h), CG
+    tolerance 1e-12: velocity and pressure against the oracle's ten steps."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    n, p, nu, steps = 16, 2, 1e-2, 10
+    _say("[imex tgv16 p2]")
+    od, disc = _pair(n, p, seed=1)
+    K = solve.assemble_K(od)
+    dt = 0.5 * 2 * np.pi / n
+    v = _tgv0(od, nu)
+    vg = torch.from_numpy(v.copy()).to("cuda:0")
+    pg = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    st = sld.State(disc)
+    for k in range(steps):
+        v, pi, _ = oimex.imex_step(od, K, v, dt, nu)
+        st.sld_imex_step(vg, pg, dt, nu, rtol=1e-12, visc_rtol=1e-12)
+    rv, rp = _rel(vg.cpu().numpy(), v), _rel(pg.cpu().numpy(), pi)
+    err = oimex.dual_l2_error(od, vg.cpu().numpy(),
+                              lambda xy: oimex.tgv_velocity(xy, steps * dt, nu))
+    _say(f"    after {steps} steps: v {rv:.2e} p {rp:.2e}; L2 error vs vortex {err:.3e}")
+    assert rv <= 1e-9 and rp <= 1e-9
+
+
+def test_imex_tgv128_p3_fifty_steps_properties(torch_dev):
+    """128x128x2 jittered periodic mesh, p = 3, nu = 1e-2, fifty steps at CFL 0.5: after every
+    step the dual velocity is divergence-free to the CG tolerance, the kinetic energy (nodal
+    sum) decays, and at the end the velocity matches the analytic vortex to first order."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    n, p, nu, steps = 128, 3, 1e-2, 50
+    _say("[imex tgv128 p3]")
+    xy, tri, per = lattice_mesh(n, seed=2, periodic=True, length=2 * np.pi)
+    disc = sld.Disc(sld.Mesh(xy, tri, per, device=0), p)
+    nodes = disc.dual_nodes()  # [nd, Npsi, 2]
+    v0 = np.ascontiguousarray(oimex.tgv_velocity(nodes, 0.0, nu).transpose(0, 2, 1))
+    vg = torch.from_numpy(v0).to("cuda:0")
+    pg = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    st = sld.State(disc)
+    dt = 0.5 * 2 * np.pi / n
+    e0 = e_prev = float((vg * vg).sum())
+    for k in range(steps):
+        rep = st.sld_imex_step(vg, pg, dt, nu, rtol=1e-12, visc_rtol=1e-12)
+        assert rep["pressure"]["converged"]
+        dv = float(torch.linalg.norm(disc.sld_divergence(vg)))
+        e = float((vg * vg).sum())
+        if k % 10 == 0 or k == steps - 1:
+            _say(f"    step {k}: |Dv| {dv:.2e} energy {e:.6e} p iters {rep['pressure']['iters']} "
+                 f"visc {[r['iters'] for r in rep['viscous']]} {rep['seconds'] * 1e3:.1f} ms")
+        assert dv <= 1e-6
+        assert e <= e_prev * (1 + 1e-3)  # nodal-sum proxy of the energy: no growth beyond noise
+        e_prev = e
+    assert 0.5 * e0 <= e_prev <= e0
+    ve = oimex.tgv_velocity(nodes, steps * dt, nu).transpose(0, 2, 1)
+    err = math.sqrt(float(((vg.cpu().numpy() - ve) ** 2).mean()) / float((ve ** 2).mean()))
+    _say(f"    nodal relative RMS error vs vortex at t = {steps * dt:.3f}: {err:.3e}")
+    assert err <= 0.05
+
+
+def test_imex_step_argument_errors(torch_dev):
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    od, disc = _pair(4, 2, periodic=False, seed=9)
+    st = sld.State(disc)
+    v = torch.zeros(disc.dual_shape, dtype=torch.float64, device="cuda:0")
+    p = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(sld.SldError, match="periodic"):
+        st.sld_imex_step(v, p, 0.1, 1e-2)
+    od, disc = _pair(4, 2, seed=9)
+    st = sld.State(disc)
+    v = torch.zeros(disc.dual_shape, dtype=torch.float64, device="cuda:0")
+    p = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(sld.SldError, match="R = 0"):
+        st.sld_imex_step(v, p, 0.1, 1e-2, R=2)
+    with pytest.raises(sld.SldError, match="dt"):
+        st.sld_imex_step(v, p, 0.0, 1e-2)
+    rep = st.sld_imex_step(v, p, 0.1, 1e-2)  # rest stays at rest
+    assert float(v.abs().max()) == 0.0 and float(p.abs().max()) == 0.0
+    assert rep["status"] == "SLD_OK"

@@ -132,3 +132,32 @@ def test_reference_operators_match_oracle_integrals(p):
     assert np.abs(d.sld_ref_operator("sl_points").reshape(-1, 2) - sp).max() < 1e-15
     proj = advect.projection_matrix(p)
     assert np.abs(d.sld_ref_operator("sl_proj").reshape(N, -1) - proj).max() < 1e-12 * np.abs(proj).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_transfer_tables_match_oracle_integrals(p):
+    """Mref and the dual -> main tables Ldm[alpha] against the oracle's quadrature: Mref is the
+    T_ref mass matrix; Ldm[alpha] maps the nodal values on the sub-triangle (c, v_alpha,
+    v_alpha+1) to the L2 projection onto the main basis of the function equal to the
+    sub-triangle's Lagrange interpolant there and zero elsewhere on T_ref."""
+    from oracle import basis
+    from oracle.quadrature import triangle_rule
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(3, seed=1)
+    d = sld.Disc(sld.Mesh(xy, tri, per, device=-1), p)
+    N = d.nphi
+    pts, w = triangle_rule(p + 2)
+    ph = basis.phi(p, pts[:, 0], pts[:, 1])
+    M = np.einsum("q,qk,ql->kl", w, ph, ph)
+    assert np.abs(d.sld_ref_operator("Mref").reshape(N, N) - M).max() < 1e-15
+    verts = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    c = verts.mean(axis=0)
+    for alpha in range(3):
+        a, b = verts[alpha], verts[(alpha + 1) % 3]
+        # points of the sub-triangle through its own map zeta -> c + z1 (a - c) + z2 (b - c)
+        x = c[None, :] + pts[:, :1] * (a - c)[None, :] + pts[:, 1:] * (b - c)[None, :]
+        jac = abs((a - c)[0] * (b - c)[1] - (a - c)[1] * (b - c)[0])
+        V = np.einsum("q,qk,qn->kn", w * jac, basis.phi(p, x[:, 0], x[:, 1]), ph)
+        want = np.linalg.solve(M, V)
+        got = d.sld_ref_operator("Ldm", alpha).reshape(N, N)
+        assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
