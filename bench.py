@@ -188,6 +188,101 @@ def bench_sl_advect(args, torch, sld, lattice_mesh, random_fourier_field, nc=3):
     print(json.dumps(res), flush=True)
 
 
+def tgv_velocity(xy, t, nu):
+    """Taylor-Green vortex velocity on [0, 2 pi]^2 (no gravity), [..., 2]."""
+    x, y = xy[..., 0], xy[..., 1]
+    e = math.exp(-2.0 * nu * t)
+    return np.stack([np.sin(x) * np.cos(y) * e, -np.cos(x) * np.sin(y) * e], axis=-1)
+
+
+def imex_cpu_baseline(wl, xy, tri, per, v0, dt, nu):
+    """The oracle's R = 0 step timed on the same mesh when it is small enough to run whole
+    (operator assembly excluded); None otherwise."""
+    if wl["n"] > 16:
+        return None
+    from oracle import imex as oimex
+    from oracle import solve as osolve
+    from oracle.mesh import OracleMesh
+    from oracle.operators import OracleDisc
+    od = OracleDisc(OracleMesh(xy, tri, per), wl["p"])
+    K = osolve.assemble_K(od)
+    t0 = time.perf_counter()
+    nsteps = 2
+    v = v0
+    for _ in range(nsteps):
+        v, _, _ = oimex.imex_step(od, K, v, dt, nu)
+    sec = time.perf_counter() - t0
+    return {"value": nsteps / sec, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsteps} whole R = 0 steps of the oracle on the same mesh (assembly of K "
+                      "excluded; pure-Python walks, sparse LU viscous and dense bordered "
+                      "pressure solves), single thread"}
+
+
+def bench_imex(args, torch, sld, lattice_mesh):
+    """One step = one R = 0 semi-Lagrangian IMEX step of the Taylor-Green vortex (nu = 1e-2,
+    CFL 0.5, CG tolerance 1e-12, pressure warm-started from the previous step)."""
+    wl = WORKLOADS[args.workload]
+    n, p = wl["n"], wl["p"]
+    nu = 1e-2
+    xy, tri, per = lattice_mesh(n, seed=wl["seed"])
+    mesh = sld.Mesh(xy, tri, per, device=0)
+    disc = sld.Disc(mesh, p)
+    ne, nphi = mesh.ne, disc.nphi
+    nodes = disc.dual_nodes()
+    v0_h = np.ascontiguousarray(tgv_velocity(nodes, 0.0, nu).transpose(0, 2, 1))
+    v = torch.from_numpy(v0_h).to("cuda:0")
+    pres = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    state = sld.State(disc)
+    dt = 0.5 * 2 * math.pi / n
+    steps = max(args.steps, 1) * 10
+    for _ in range(args.warmup):
+        state.sld_imex_step(v, pres, dt, nu, graph_block=args.graph_block)
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        reps.append(state.sld_imex_step(v, pres, dt, nu, graph_block=args.graph_block,
+                                        profile=True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    t_end = (args.warmup + steps) * dt
+    ve = tgv_velocity(nodes, t_end, nu).transpose(0, 2, 1)
+    vh = v.cpu().numpy()
+    err = math.sqrt(float(((vh - ve) ** 2).mean()) / float((ve ** 2).mean()))
+    divfree = float(torch.linalg.norm(disc.sld_divergence(v)))
+    p_iters = sum(r["pressure"]["iters"] for r in reps)
+    v_iters = sum(r["viscous"][0]["iters"] + r["viscous"][1]["iters"] for r in reps)
+    timed = sum(r["pressure"]["timed_iters"] for r in reps)
+    step_us = sum(r["pressure"]["step_us"] * r["pressure"]["timed_iters"] for r in reps) / max(timed, 1)
+    sbytes = step_bytes_per_tri(nphi) * ne
+    achieved = sbytes / (step_us * 1e-6) / 1e9
+    res = {
+        "metric": "SL-IMEX (R = 0) Taylor-Green steps/s",
+        "value": steps / elapsed, "unit": "steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: Taylor-Green vortex, nu = {nu:g}, periodic "
+                               f"jittered {n}x{n}x2 = {ne} triangles, p={p}, dt = 0.5 h, "
+                               f"{steps} R = 0 steps, CG rtol 1e-12",
+                   "triangles": ne, "p": p, "dt": dt, "nu": nu},
+        "pressure_cg_iters_per_step": p_iters / steps,
+        "viscous_cg_iters_per_step": v_iters / steps,
+        "pressure_cg_dof_updates_per_s": ne * nphi * p_iters /
+            sum(r["pressure"]["seconds"] for r in reps),
+        "velocity_rel_rms_error_vs_vortex": err, "t_end": t_end,
+        "divergence_norm_at_end": divfree,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload),
+                     "kernel": f"k_cg_step<{p}, double> (pressure CG iteration)",
+                     "kernel_us_source": "HIP events around captured blocks of iterations",
+                     "kernel_us": step_us, "bytes_per_launch": sbytes},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = imex_cpu_baseline(wl, xy, tri, per, v0_h, dt, nu)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +297,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sl-advect", action="store_true",
                     help="measure the semi-Lagrangian advection kernel instead (3 fields, CFL 0.5)")
+    ap.add_argument("--imex", action="store_true",
+                    help="measure R = 0 SL-IMEX Taylor-Green steps instead (10 x --steps steps)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy MIB MiB device-to-device three times "
                          "(reference kernel for HBM byte counters)")
@@ -218,6 +315,11 @@ def main():
 
     if args.sl_advect:
         bench_sl_advect(args, torch, sld, lattice_mesh, random_fourier_field)
+        return
+    if args.imex:
+        if WORKLOADS[args.workload].get("walls"):
+            sys.exit("--imex runs the periodic Taylor-Green workloads")
+        bench_imex(args, torch, sld, lattice_mesh)
         return
     if args.rtol is None:
         args.rtol = 1e-12 if args.precision == "fp64" else 1e-11

@@ -419,11 +419,13 @@ class State:
         self.handle = h
 
     def sld_imex_step(self, v, p, dt, nu, R=0, rtol=1e-12, visc_rtol=1e-12, maxit=200000,
-                      graph_block=32, warm_start=True, precision="fp64", stream=None):
+                      graph_block=32, warm_start=True, precision="fp64", profile=False,
+                      stream=None):
         """One IMEX step in place: v [nd, 2, N_psi] at t -> t + dt; p [ne, N_phi] <- pressure."""
         d = self.disc
         prm = sld_imex_params(float(nu), int(R),
-                              make_params(rtol, maxit, warm_start, graph_block, False, precision),
+                              make_params(rtol, maxit, warm_start, graph_block,
+                                          profile and precision == "fp64", precision),
                               make_params(visc_rtol, maxit, True, graph_block))
         rep = sld_imex_report()
         st = _lib.sld_imex_step(self.handle, ctypes.byref(prm), float(dt),
