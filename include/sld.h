@@ -276,7 +276,7 @@ sld_status sld_imex_step(sld_state state, const sld_imex_params* params, double 
 
 /* ------------------------------------------------------------------ serving
  * Continuous batching of independent pressure solves (the paper's pressure stage of
- * eq. pressure_final, one per request).  Requests are queued as they arrive; a worker thread
+ * eq. pressure_final, one per request) and IMEX steps (sld_server_submit_imex).  Requests are queued as they arrive; a worker thread
  * admits the first queued request whose disc is idle and whose footprint fits the remaining
  * memory budget (one request is always admitted when none runs), and runs sld_cg_solve on its
  * own HIP stream, so requests overlap on the device.  Requests on the same disc run in turn
@@ -295,6 +295,13 @@ sld_status sld_server_create(int32_t device, uint64_t hbm_budget_bytes, int32_t 
  * alone exceeds the budget. */
 sld_status sld_server_submit(sld_server server, sld_disc disc, const double* b, double* p,
                              const sld_cg_params* params, void* stream, uint64_t* ticket);
+/* Queue one IMEX step (sld_imex_step) on `state`.  v, p: device buffers as for sld_imex_step
+ * that must stay valid until the ticket completes; the step waits for work already queued on
+ * `stream` before it starts.  The ticket's report is the step's pressure-solve report.  An
+ * IMEX request holds its state's disc while it runs, like a solve on that disc.
+ * SLD_E_BUDGET if the request alone exceeds the budget. */
+sld_status sld_server_submit_imex(sld_server server, sld_state state, const sld_imex_params* params,
+                                  double dt, double* v, double* p, void* stream, uint64_t* ticket);
 /* Completion of a ticket: *done = 1 when p holds the result (then *status is the solve's
  * sld_status and *report its report, and the ticket is retired).  wait != 0 blocks until done. */
 sld_status sld_server_poll(sld_server server, uint64_t ticket, int32_t wait, int32_t* done,

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "sld_internal.h"
+#include "state_internal.h"
 
 namespace {
 thread_local std::string g_err;
@@ -1068,15 +1069,6 @@ sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_par
 }  // extern "C"
 
 // ---------------------------------------------------------------- IMEX step (Section 4)
-
-struct sld_state_s {
-    sld_disc disc = nullptr;
-    double* vbar = nullptr;   // [ne][2][N] velocity on the main grid
-    double* vfoot = nullptr;  // [ne][2][N] its semi-Lagrangian projection
-    double* vsbar = nullptr;  // [2][ne][N] viscous solution, component-major
-    double* vs = nullptr;     // [nd][2][Npsi] the intermediate dual velocity v*
-    double* b = nullptr;      // [ne][N] right-hand side (viscous, then pressure)
-};
 
 namespace {
 

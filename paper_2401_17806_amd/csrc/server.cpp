@@ -1,9 +1,10 @@
 // Continuous-batching server for independent pressure solves (the serving form of the
-// Schur-CG): requests are queued as they arrive, admitted while the device-memory budget and a
-// free worker allow, and run concurrently on per-worker HIP streams, so work of different
-// requests overlaps on the GPU.  A request owns its disc (CG workspace) while it runs; requests
-// on the same disc run one after another.  Results do not depend on the mix: the CG kernels use
-// fixed grids and fixed-order reductions, so a solve is bitwise the same alone or overlapped.
+// Schur-CG) and IMEX time steps: requests are queued as they arrive, admitted while the
+// device-memory budget and a free worker allow, and run concurrently on per-worker HIP
+// streams, so work of different requests overlaps on the GPU.  A request owns its disc (CG
+// workspace, and an IMEX step also its state) while it runs; requests on the same disc run one
+// after another.  Results do not depend on the mix: every kernel uses fixed grids and
+// fixed-order reductions, so a request's result is bitwise the same alone or overlapped.
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "sld_internal.h"
+#include "state_internal.h"
 
 namespace {
 
@@ -23,6 +25,11 @@ struct Request {
     const double* b = nullptr;
     double* p = nullptr;
     sld_cg_params params{};
+    // IMEX step requests (state != nullptr): the step's parameters, time step and velocity
+    sld_state state = nullptr;
+    sld_imex_params iparams{};
+    double dt = 0.0;
+    double* v = nullptr;
     uint64_t bytes = 0;
     hipEvent_t ready = nullptr;  // recorded on the submitter's stream at submit
 };
@@ -93,8 +100,15 @@ void worker_main(sld_server_s* s) {
         }
         sld_cg_report rep{};
         int st = SLD_E_HIP;
-        if (stream && hipStreamWaitEvent(stream, req.ready, 0) == hipSuccess)
-            st = sld_cg_solve(req.disc, req.b, req.p, &req.params, &rep, stream);
+        if (stream && hipStreamWaitEvent(stream, req.ready, 0) == hipSuccess) {
+            if (req.state) {
+                sld_imex_report irep{};
+                st = sld_imex_step(req.state, &req.iparams, req.dt, req.v, req.p, &irep, stream);
+                rep = irep.pressure;
+            } else {
+                st = sld_cg_solve(req.disc, req.b, req.p, &req.params, &rep, stream);
+            }
+        }
         (void)hipEventDestroy(req.ready);
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -153,29 +167,12 @@ sld_status sld_server_create(int32_t device, uint64_t hbm_budget_bytes, int32_t 
     return SLD_OK;
 }
 
-sld_status sld_server_submit(sld_server s, sld_disc d, const double* b, double* p,
-                             const sld_cg_params* params, void* stream, uint64_t* ticket) {
-    if (!s || !d || !b || !p || !params || !ticket) {
-        sld_set_error("sld_server_submit: NULL argument");
-        return SLD_E_INVALID;
-    }
-    if (d->mesh->device != s->device) {
-        sld_set_error("sld_server_submit: disc lives on another device");
-        return SLD_E_INVALID;
-    }
-    uint64_t bytes = 0;
-    (void)sld_disc_footprint(d, &bytes);
-    bytes += uint64_t(d->mesh->ne) * d->nphi * 16;  // the request's b and p
-    if (bytes > s->budget) {
-        sld_set_error("sld_server_submit: the request alone exceeds the memory budget");
-        return SLD_E_BUDGET;
-    }
-    Request r;
-    r.disc = d;
-    r.b = b;
-    r.p = p;
-    r.params = *params;
-    r.bytes = bytes;
+}  // extern "C"
+
+namespace {
+
+// Record the submitter's stream position and queue the request.
+sld_status enqueue(sld_server s, Request r, void* stream, uint64_t* ticket) {
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(s->device);
@@ -201,6 +198,67 @@ sld_status sld_server_submit(sld_server s, sld_disc d, const double* b, double* 
     }
     s->cv_work.notify_one();
     return SLD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sld_status sld_server_submit(sld_server s, sld_disc d, const double* b, double* p,
+                             const sld_cg_params* params, void* stream, uint64_t* ticket) {
+    if (!s || !d || !b || !p || !params || !ticket) {
+        sld_set_error("sld_server_submit: NULL argument");
+        return SLD_E_INVALID;
+    }
+    if (d->mesh->device != s->device) {
+        sld_set_error("sld_server_submit: disc lives on another device");
+        return SLD_E_INVALID;
+    }
+    uint64_t bytes = 0;
+    (void)sld_disc_footprint(d, &bytes);
+    bytes += uint64_t(d->mesh->ne) * d->nphi * 16;  // the request's b and p
+    if (bytes > s->budget) {
+        sld_set_error("sld_server_submit: the request alone exceeds the memory budget");
+        return SLD_E_BUDGET;
+    }
+    Request r;
+    r.disc = d;
+    r.b = b;
+    r.p = p;
+    r.params = *params;
+    r.bytes = bytes;
+    return enqueue(s, r, stream, ticket);
+}
+
+sld_status sld_server_submit_imex(sld_server s, sld_state state, const sld_imex_params* params,
+                                  double dt, double* v, double* p, void* stream, uint64_t* ticket) {
+    if (!s || !state || !params || !v || !p || !ticket) {
+        sld_set_error("sld_server_submit_imex: NULL argument");
+        return SLD_E_INVALID;
+    }
+    sld_disc d = state->disc;
+    if (d->mesh->device != s->device) {
+        sld_set_error("sld_server_submit_imex: state lives on another device");
+        return SLD_E_INVALID;
+    }
+    uint64_t bytes = 0;
+    (void)sld_disc_footprint(d, &bytes);
+    // + the state's workspace and the request's v and p
+    bytes += sld_state_bytes(state) + 8 * (uint64_t(d->mesh->nd) * 2 * d->npsi +
+                                           uint64_t(d->mesh->ne) * d->nphi);
+    if (bytes > s->budget) {
+        sld_set_error("sld_server_submit_imex: the request alone exceeds the memory budget");
+        return SLD_E_BUDGET;
+    }
+    Request r;
+    r.disc = d;
+    r.p = p;
+    r.state = state;
+    r.iparams = *params;
+    r.dt = dt;
+    r.v = v;
+    r.bytes = bytes;
+    return enqueue(s, r, stream, ticket);
 }
 
 sld_status sld_server_poll(sld_server s, uint64_t ticket, int32_t wait, int32_t* done,

@@ -97,6 +97,8 @@ _sig("sld_imex_step", [_vp, ctypes.POINTER(sld_imex_params), ctypes.c_double, _v
 _sig("sld_server_create", [_i32, ctypes.c_uint64, _i32, ctypes.POINTER(_vp)])
 _sig("sld_server_submit", [_vp, _vp, _vp, _vp, ctypes.POINTER(sld_cg_params), _vp,
                            ctypes.POINTER(ctypes.c_uint64)])
+_sig("sld_server_submit_imex", [_vp, _vp, ctypes.POINTER(sld_imex_params), ctypes.c_double, _vp,
+                                _vp, _vp, ctypes.POINTER(ctypes.c_uint64)])
 _sig("sld_server_poll", [_vp, ctypes.c_uint64, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                          ctypes.POINTER(sld_cg_report)])
 _sig("sld_server_stats", [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
@@ -110,7 +112,8 @@ EXPORTED = [
     "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_disc_footprint",
     "sld_sl_advect", "sld_ref_operator", "sld_dual_to_main", "sld_main_to_dual",
     "sld_viscous_solve", "sld_state_create", "sld_state_destroy", "sld_imex_step",
-    "sld_server_create", "sld_server_submit", "sld_server_poll", "sld_server_stats",
+    "sld_server_create", "sld_server_submit", "sld_server_submit_imex", "sld_server_poll",
+    "sld_server_stats",
     "sld_server_destroy",
 ]
 
@@ -467,6 +470,20 @@ class Server:
                                       disc._dev(p, disc.main_shape, "p"), ctypes.byref(prm),
                                       disc._stream(stream), ctypes.byref(t)))
         self._keep[t.value] = (b, p)  # buffers stay alive until the ticket completes
+        return t.value
+
+    def sld_server_submit_imex(self, state: "State", v, p, dt, nu, R=0, rtol=1e-12,
+                               visc_rtol=1e-12, maxit=200000, graph_block=32, warm_start=True,
+                               precision="fp64", stream=None):
+        d = state.disc
+        prm = sld_imex_params(float(nu), int(R),
+                              make_params(rtol, maxit, warm_start, graph_block, False, precision),
+                              make_params(visc_rtol, maxit, True, graph_block))
+        t = ctypes.c_uint64()
+        _check(_lib.sld_server_submit_imex(self.handle, state.handle, ctypes.byref(prm), float(dt),
+                                           d._dev(v, d.dual_shape, "v"), d._dev(p, d.main_shape, "p"),
+                                           d._stream(stream), ctypes.byref(t)))
+        self._keep[t.value] = (state, v, p)  # alive until the ticket completes
         return t.value
 
     def sld_server_poll(self, ticket: int, wait: bool = False):

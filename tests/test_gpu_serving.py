@@ -115,3 +115,65 @@ def test_serving_loop_poisson_small(torch_dev):
                                        maxit=200000)
             assert rep["iters"] == rec["iters"]
             assert torch.equal(x, rec["solution"]), q["id"]
+
+
+def _tgv_dual(disc, nu=1e-2):
+    x = disc.dual_nodes()
+    u = np.sin(x[..., 0]) * np.cos(x[..., 1])
+    w = -np.cos(x[..., 0]) * np.sin(x[..., 1])
+    return np.ascontiguousarray(np.stack([u, w], axis=1))  # [nd, 2, Npsi]
+
+
+def test_server_imex_steps_equal_direct_steps(torch_dev):
+    """IMEX-step requests (two consecutive steps per state, queued back to back) mixed with
+    pressure solves on other discs: every result equals, bitwise, the same work done alone."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    _say("[server] imex steps in the mix")
+    nu = 1e-2
+    ispecs = [(8, 2), (12, 3), (10, 1)]
+    idiscs = [_disc(n, p) for n, p in ispecs]
+    sspecs = [(16, 3), (14, 2)]
+    sdiscs = [_disc(n, p) for n, p in sspecs]
+    rhs = [_rhs(torch, d, 70 + k) for k, d in enumerate(sdiscs)]
+    v0 = [torch.from_numpy(_tgv_dual(d)).to("cuda:0") for d in idiscs]
+    dts = [0.5 * 2 * np.pi / n for n, _ in ispecs]
+    # alone
+    alone_v, alone_p = [], []
+    for d, v, dt in zip(idiscs, v0, dts):
+        st = sld.State(d)
+        vv = v.clone()
+        pp = torch.zeros(d.main_shape, dtype=torch.float64, device="cuda:0")
+        for _ in range(2):
+            rep = st.sld_imex_step(vv, pp, dt, nu, graph_block=16)
+            assert rep["status"] == "SLD_OK"
+        alone_v.append(vv)
+        alone_p.append(pp)
+    alone_x = []
+    for d, b in zip(sdiscs, rhs):
+        x, rep = d.sld_cg_solve(b, graph_block=16)
+        assert rep["status"] == "SLD_OK"
+        alone_x.append(x)
+    torch.cuda.synchronize()
+    # in the mix
+    server = sld.Server(device=0, budget_bytes=8 << 30, workers=4)
+    states = [sld.State(d) for d in idiscs]
+    vs = [v.clone() for v in v0]
+    ps = [torch.zeros(d.main_shape, dtype=torch.float64, device="cuda:0") for d in idiscs]
+    xs = [torch.empty_like(b) for b in rhs]
+    tickets = []
+    for step in range(2):
+        for k in range(len(idiscs)):
+            tickets.append(server.sld_server_submit_imex(states[k], vs[k], ps[k], dts[k], nu,
+                                                         graph_block=16))
+            if step == 0 and k < len(sdiscs):
+                tickets.append(server.sld_server_submit(sdiscs[k], rhs[k], xs[k], graph_block=16))
+    reps = [server.sld_server_poll(t, wait=True) for t in tickets]
+    stats = server.sld_server_stats()
+    server.close()
+    assert stats["completed"] == len(tickets) and stats["queued"] == 0
+    assert all(r["status"] == "SLD_OK" for r in reps), reps
+    for k in range(len(idiscs)):
+        assert torch.equal(vs[k], alone_v[k]) and torch.equal(ps[k], alone_p[k]), k
+    for k in range(len(sdiscs)):
+        assert torch.equal(xs[k], alone_x[k]), k
