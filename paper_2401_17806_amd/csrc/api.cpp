@@ -569,6 +569,8 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         if (cap > 0 && cap < G) G = (cap + 7) & ~7;
     }
     w.grid = G;
+    if (const char* sx = std::getenv("SLD_CG_STREAM_X"))  // debugging aid: force x streaming
+        w.stream_x = std::atoi(sx) != 0 ? 1 : 0;
     std::lock_guard<std::mutex> lk(device_setup_mutex());
     Uploader up;
     std::vector<unsigned char> h32(ops32_bytes(p));

@@ -125,7 +125,7 @@ inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes, bool front) 
 // that does not depend on alpha and beta -- the tile's state, its halo ids, the previous
 // launch's dot partials and the scalars -- is issued at entry, so their latencies overlap;
 // otherwise (several tiles per block) the loads follow the tile loop.
-template <int P, typename Real, class Ops, bool kFront, bool kShift>
+template <int P, typename Real, class Ops, bool kFront, bool kShift, bool kStream>
 __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const Ops* __restrict__ ops,
                                                        const double4* __restrict__ geo,
                                                        const int4* __restrict__ nbr,
@@ -269,25 +269,49 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
                 }
             }
         } else {
-            // several tiles per block: plain loops (fewer live registers, higher occupancy)
+            // several tiles per block: plain loops (fewer live registers, higher occupancy).
+            // x is private to the tile; when the working set outgrows the memory-side cache it
+            // is streamed with non-temporal accesses, leaving that cache to the vectors the
+            // neighbours' halos read
             for (int f = threadIdx.x; f < nown; f += NT) {
                 const int64_t o = base + f;
                 const Real dprev = d_in[o];
                 const Real rk = mad(-ra, q_in[o], r_in[o]);
                 const Real dk = mad(rb, dprev, rk);
-                x[o] = mad(ra, dprev, x[o]);
+                // (a compile-time choice: a runtime branch lets the compiler merge the two
+                // accesses and drop the non-temporal hint)
+                if constexpr (kStream)
+                    __builtin_nontemporal_store(mad(ra, dprev, __builtin_nontemporal_load(&x[o])), &x[o]);
+                else
+                    x[o] = mad(ra, dprev, x[o]);
                 r_out[o] = rk;
                 d_out[o] = dk;
                 sd[f] = dk;
                 sr[f] = rk;
                 acc[0] = fma((double)rk, (double)rk, acc[0]);
             }
-            for (int e = threadIdx.x; e < nhe; e += NT) {
-                const int id = halo_pad[tile * hs + e / N];
-                if (id >= 0) {
-                    const int64_t o = (int64_t)id * N + (e - (e / N) * N);
-                    sd[T * N + e] = mad(rb, d_in[o], mad(-ra, q_in[o], r_in[o]));
+            // halo ids of two entries first, then their values (two gathers in flight)
+            for (int e0 = threadIdx.x; e0 < nhe; e0 += 2 * NT) {
+                int id2[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int e = e0 + u * NT;
+                    id2[u] = e < nhe ? halo_pad[tile * hs + e / N] : -1;
                 }
+                Real hd[2], hq[2], hr[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (id2[u] >= 0) {
+                        const int e = e0 + u * NT;
+                        const int64_t o = (int64_t)id2[u] * N + (e - (e / N) * N);
+                        hd[u] = d_in[o];
+                        hq[u] = q_in[o];
+                        hr[u] = r_in[o];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (id2[u] >= 0) sd[T * N + e0 + u * NT] = mad(rb, hd[u], mad(-ra, hq[u], hr[u]));
             }
         }
         __syncthreads();
@@ -681,6 +705,15 @@ hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p
     return hipGetLastError();
 }
 
+// Stream x (non-temporal) when the CG working set -- five vectors and the geometry -- exceeds
+// half of the 256 MB memory-side cache: measured 6% faster on 512x512x2, p = 3 (240 MB), and
+// 12% slower on 256x256x2, p = 4 (85 MB, cache-resident), where it pays to keep x cached.
+inline int stream_x_for(const sld_disc_s* d, size_t word) {
+    if (d->cg.stream_x >= 0) return d->cg.stream_x;
+    const int64_t ne = d->mesh->ne;
+    return (int64_t)5 * ne * d->nphi * (int64_t)word + ne * 48 > (int64_t(128) << 20) ? 1 : 0;
+}
+
 hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     const CgWork& w = d->cg;
@@ -688,9 +721,10 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream
     const int o = 1 - parity;
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
+    const bool sx = stream_x_for(d, sizeof(double)) != 0;
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double), front);
-#define SLD_STEP64(F, SH)                                                                       \
-    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F, SH>), dim3(G),  \
+#define SLD_STEP64(F, SH, ST)                                                                   \
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F, SH, ST>), dim3(G), \
                                           dim3(F ? kBlockCG : kBlockTri), lds, s, ops_of<PP>(d), \
                                           m->geo_i,                                             \
                                           m->nbr_i, m->halo_pad, m->hmax, m->ne, w.x,           \
@@ -699,15 +733,21 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream
                                           w.part + o * 4 * G, w.scal, parity))
     if (front) {
         if (shift) {
-            SLD_STEP64(true, true);
+            SLD_STEP64(true, true, false);
         } else {
-            SLD_STEP64(true, false);
+            SLD_STEP64(true, false, false);
+        }
+    } else if (sx) {
+        if (shift) {
+            SLD_STEP64(false, true, true);
+        } else {
+            SLD_STEP64(false, false, true);
         }
     } else {
         if (shift) {
-            SLD_STEP64(false, true);
+            SLD_STEP64(false, true, false);
         } else {
-            SLD_STEP64(false, false);
+            SLD_STEP64(false, false, false);
         }
     }
 #undef SLD_STEP64
@@ -726,11 +766,11 @@ int cg_grid_for(const sld_disc_s* d, bool* front) {
     const size_t lds_f = step_lds_bytes(d->nphi, m->hmax, sizeof(double), true);
     const size_t lds_l = step_lds_bytes(d->nphi, m->hmax, sizeof(double), false);
     SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &per_front, (k_cg_step<PP, double, RefOps<PP>, true, false>), kBlockCG,
+                           &per_front, (k_cg_step<PP, double, RefOps<PP>, true, false, false>), kBlockCG,
                            lds_f));
     if (e == hipSuccess)
         SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                               &per_lanes, (k_cg_step<PP, double, RefOps<PP>, false, false>), kBlockTri,
+                               &per_lanes, (k_cg_step<PP, double, RefOps<PP>, false, false, false>), kBlockTri,
                                lds_l));
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device);
     const bool ok = e == hipSuccess && cus > 0;
@@ -775,8 +815,9 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float), front);
-#define SLD_STEP32(F)                                                                           \
-    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>, F, false>), dim3(G), \
+    const bool sx = stream_x_for(d, sizeof(float)) != 0;
+#define SLD_STEP32(F, ST)                                                                       \
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>, F, false, ST>), dim3(G), \
                                           dim3(F ? kBlockCG : kBlockTri), lds, s, ops32_of<PP>(d), \
                                           m->geo_i,                                             \
                                           m->nbr_i, m->halo_pad, m->hmax, m->ne, w.e32,         \
@@ -785,9 +826,11 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
                                           w.part32 + parity * 4 * G, w.part32 + o * 4 * G,      \
                                           w.scal_in, parity))
     if (front) {
-        SLD_STEP32(true);
+        SLD_STEP32(true, false);
+    } else if (sx) {
+        SLD_STEP32(false, true);
     } else {
-        SLD_STEP32(false);
+        SLD_STEP32(false, false);
     }
 #undef SLD_STEP32
     return hipGetLastError();

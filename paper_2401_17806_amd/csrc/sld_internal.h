@@ -73,6 +73,7 @@ struct CgWork {
     double* host_scal = nullptr;   // pinned mirror of scal
     int grid = 0;                  // blocks of every CG kernel
     bool front = false;            // iteration kernel variant: one tile per block, four roles
+    int stream_x = -1;             // x with non-temporal accesses: -1 by working-set size, 0/1
     std::vector<hipEvent_t> events;  // profiling events (created on first profiled solve)
     // mixed precision: FP32 inner CG state (e32 = the correction), its partials and scalars
     float* r32[2] = {nullptr, nullptr};

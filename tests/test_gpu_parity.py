@@ -244,3 +244,38 @@ def test_parity_on_shuffled_unstructured_numbering(torch_dev, periodic, p):
     p_gpu, rep = disc.sld_cg_solve(_to(torch, b), rtol=1e-13, maxit=20000, graph_block=8)
     assert rep["converged"]
     assert _rel(p_gpu.cpu().numpy(), x_or) <= SOLVE_TOL
+
+
+@pytest.mark.parametrize("stream", [0, 1])
+@pytest.mark.parametrize("n,p,periodic", [(18, 1, True), (17, 3, True), (17, 4, True),
+                                          (18, 2, False)])
+def test_chunked_cg_variant_parity(torch_dev, monkeypatch, n, p, periodic, stream):
+    """The iteration kernel's several-tiles-per-block variant (the one large meshes run),
+    forced on small meshes by capping the grid at 8 blocks, with and without non-temporal
+    streaming of x: FP64, mixed and viscous (mass-shifted) solves against the oracle."""
+    torch = torch_dev
+    from oracle import imex as oimex
+    from paper_2401_17806_amd import sld
+    _say(f"[chunked cg] n={n} p={p} periodic={periodic} stream={stream}")
+    monkeypatch.setenv("SLD_CG_GRID", "8")
+    monkeypatch.setenv("SLD_CG_STREAM_X", str(stream))
+    xy, tri, per = lattice_mesh(n, seed=23, periodic=periodic,
+                                length=(2 * np.pi if periodic else 1.0))
+    od = OracleDisc(OracleMesh(xy, tri, per), p)
+    K = solve.assemble_K(od)
+    disc = sld.Disc(sld.Mesh(xy, tri, per, device=0), p)
+    assert (mesh_tiles := (od.mesh.ne + 63) // 64) > 8, mesh_tiles
+    f = random_fourier_field(19, kmax=4, length=(2 * np.pi if periodic else 1.0))
+    b = solve.divergence(od, f(od.dual_node_xy()).transpose(0, 2, 1))
+    x_or = solve.gauge(od, solve.cg(K, b, tol=1e-13)[0])
+    p64, rep = disc.sld_cg_solve(_to(torch, b), rtol=1e-13, maxit=20000, graph_block=8)
+    pm, repm = disc.sld_cg_solve(_to(torch, b), rtol=1e-11, precision="mixed", maxit=20000,
+                                 graph_block=8)
+    fv = random_vector((od.mesh.ne, 1, od.nphi), seed=29)
+    xv, repv = disc.sld_viscous_solve(_to(torch, fv[:, 0]), 0.02, rtol=1e-13, graph_block=8)
+    want_v = oimex.viscous_solve(od, K, fv, 0.02)[:, 0]
+    r64, rm = _rel(p64.cpu().numpy(), x_or), _rel(pm.cpu().numpy(), x_or)
+    rv = _rel(xv.cpu().numpy(), want_v)
+    _say(f"    fp64 {r64:.2e} ({rep['iters']} it)  mixed {rm:.2e}  viscous {rv:.2e}")
+    assert rep["converged"] and repm["status"] == "SLD_OK" and repv["converged"]
+    assert r64 <= SOLVE_TOL and rm <= SOLVE_TOL and rv <= 1e-10
