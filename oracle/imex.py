@@ -113,6 +113,117 @@ def dual_to_main(disc: OracleDisc, vd: np.ndarray) -> np.ndarray:
     return np.linalg.solve(Mbar[:, None], rhs[..., None])[..., 0]
 
 
+# ---------------------------------------------------------------- walls of diffusion solves
+# Reading (the paper leaves the boundary treatment of the diffusion solves to its references).
+# The pressure operator K of eq. pressure_final has no wall cells: they carry prescribed
+# velocity.  A diffusion operator keeps them.  On a wall edge j the dual cell is the left half
+# alone, and its gradient follows eq. ad4.2 with the missing right-hand side replaced by the
+# boundary condition:
+#   * Dirichlet data u_b: the jump term takes u_l - u_b,
+#       Mhat_j g_j = Q_lj u_l + int_{Gamma_j} psi u_b n ds;
+#     the divergence block D_lj keeps its line term.
+#   * zero flux: no jump term and no line term in D_lj (the flux through the wall is the data,
+#     zero), so the cell contributes -int_{T_lj} grad phi . Mhat_j^{-1} int psi grad u_l, and the
+#     projected gradient is grad u_l itself (a polynomial of the half's space):
+#       -int_{T_lj} grad phi_k . grad phi_l.
+# The Laplacian is L(u) = K_W u + G_b, with K_W = K plus these wall cells and
+# G_b = sum_j D_lj Mhat_j^{-1} int_Gamma psi u_b n ds over the Dirichlet edges.
+
+
+def _wall_edges(disc: OracleDisc, mask) -> np.ndarray:
+    m = disc.mesh
+    mask = np.asarray(mask, dtype=bool)
+    return np.nonzero(mask & ~m.interior)[0]
+
+
+def _wall_stiffness(disc: OracleDisc, J) -> np.ndarray:
+    """-int_{T_lj} grad phi_k . grad phi_l over the wall sub-triangles of edges J [E, N, N]."""
+    m = disc.mesh
+    L = m.left[J]
+    bl = m.centroid[L]
+    A, B = m.A[J], m.B[J]
+    u, v = disc.tri_pts[:, 0], disc.tri_pts[:, 1]
+    x = bl[:, None] + u[None, :, None] * (A - bl)[:, None] + v[None, :, None] * (B - bl)[:, None]
+    d, e = A - bl, B - bl
+    jac = np.abs(d[:, 0] * e[:, 1] - d[:, 1] * e[:, 0])
+    g = disc.grad_phi_phys(L, x)  # [E, q, N, 2]
+    return -np.einsum("q,e,eqkc,eqlc->ekl", disc.tri_w, jac, g, g)
+
+
+def assemble_K_walls(disc: OracleDisc, dirichlet_mask=None) -> sp.csr_matrix:
+    """K_W: K of eq. pressure_final plus a cell on every wall edge, Dirichlet where
+    dirichlet_mask [nd] is set, zero flux elsewhere."""
+    m = disc.mesh
+    nphi = disc.nphi
+    K = solve.assemble_K(disc)
+    walls = np.nonzero(~m.interior)[0]
+    if walls.size == 0:
+        return K
+    dmask = np.zeros(m.nd, dtype=bool) if dirichlet_mask is None else np.asarray(dirichlet_mask, bool)
+    B = np.zeros((walls.size, nphi, nphi))
+    isd = dmask[walls]
+    if (~isd).any():
+        B[~isd] = _wall_stiffness(disc, walls[~isd])
+    if isd.any():
+        J = walls[isd]
+        h = _left_half(disc.p)
+        blk = disc.edge_blocks(J)
+        Mh = blk["Mhat"][:, h][:, :, h]
+        Ql = blk["Ql"][:, h]
+        Dl = blk["Dl"][:, :, h]
+        E, nh = Mh.shape[0], Mh.shape[1]
+        X = np.linalg.solve(Mh, Ql.reshape(E, nh, nphi * 2)).reshape(E, nh, nphi, 2)
+        B[isd] = np.einsum("ekmc,emlc->ekl", Dl, X)
+    kk, ll = np.meshgrid(np.arange(nphi), np.arange(nphi), indexing="ij")
+    L = m.left[walls]
+    rows = (L[:, None, None] * nphi + kk[None]).ravel()
+    cols = (L[:, None, None] * nphi + ll[None]).ravel()
+    n = m.ne * nphi
+    Kw = sp.coo_matrix((B.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+    return (K + Kw).tocsr()
+
+
+def dirichlet_rhs(disc: OracleDisc, dirichlet_mask, trace) -> np.ndarray:
+    """G_b [ne, Nphi] for the data trace(xy [..., 2]) -> [...] on the masked wall edges."""
+    m = disc.mesh
+    out = np.zeros((m.ne, disc.nphi))
+    J = _wall_edges(disc, dirichlet_mask)
+    if J.size == 0:
+        return out
+    p = disc.p
+    h = _left_half(p)
+    blk = disc.edge_blocks(J)
+    Mh = blk["Mhat"][:, h][:, :, h]
+    Dl = blk["Dl"][:, :, h]
+    t, wt = disc.line_t, disc.line_w
+    A, B = m.A[J], m.B[J]
+    xe = A[:, None] + t[None, :, None] * (B - A)[:, None]      # [E, q, 2]
+    psi_e = basis.psi(p, np.broadcast_to(1.0 - t, (J.size, t.size)),
+                      np.broadcast_to(t, (J.size, t.size)))[:, :, h]  # [E, q, nh]
+    ub = trace(xe)                                              # [E, q]
+    line = np.einsum("q,e,eqk,eq,ec->ekc", wt, m.edge_len[J], psi_e, ub, m.normal[J])
+    g = np.linalg.solve(Mh[:, None], line.transpose(0, 2, 1)[..., None])[..., 0]  # [E, 2, nh]
+    np.add.at(out, m.left[J], np.einsum("ekmc,ecm->ek", Dl, g))
+    return out
+
+
+def diffusion_solve(disc: OracleDisc, KW: sp.csr_matrix, f: np.ndarray, c: float,
+                    gb: np.ndarray | None = None) -> np.ndarray:
+    """x with (Mbar - c K_W) x = Mbar f + c G_b for f [ne, nc, Nphi] (gb [ne, Nphi] or None)."""
+    if c == 0.0:
+        return f.copy()
+    M = mass_matrix(disc)
+    lu = spla.splu((M - c * KW).tocsc())
+    ne, nc, n = f.shape
+    out = np.empty_like(f)
+    for comp in range(nc):
+        rhs = M @ f[:, comp, :].reshape(-1)
+        if gb is not None:
+            rhs = rhs + c * gb.reshape(-1)
+        out[:, comp, :] = lu.solve(rhs).reshape(ne, n)
+    return out
+
+
 def mass_matrix(disc: OracleDisc) -> sp.csr_matrix:
     """Block-diagonal Mbar (eq. Mi) as a sparse matrix over the main DOFs."""
     Mb = disc.main_mass()

@@ -162,3 +162,63 @@ def test_tgv_first_order_in_time():
     order = np.log2(errs[0] / errs[1])
     assert 0.8 <= order <= 1.4, (errs, order)
     assert errs[1] < 0.35
+
+
+def _wall_side_masks(d):
+    """Wall edges of the unit box: all walls, and the side walls x = 0, 1 only."""
+    m = d.mesh
+    wall = ~m.interior
+    mid = 0.5 * (m.A + m.B)
+    side = wall & ((np.abs(mid[:, 0]) < 1e-12) | (np.abs(mid[:, 0] - 1.0) < 1e-12))
+    return wall, side
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_dirichlet_laplacian_pins(p):
+    """Walls of diffusion solves (reading: Dirichlet cells take the jump to the data, zero-flux
+    cells keep their sub-triangle stiffness): K_W is symmetric negative definite; a linear field
+    with its own trace gives L(u) = K_W u + G_b = 0 with all walls Dirichlet, and also with
+    Dirichlet side walls and zero flux on top and bottom for u = a + b x (zero normal derivative
+    there); for p >= 2 a quadratic gives L(u) = (Delta u) int phi exactly (all walls
+    Dirichlet), and with all walls zero-flux the constants span the kernel."""
+    d = _disc(5, p, periodic=False, seed=13)
+    m = d.mesh
+    wall, side = _wall_side_masks(d)
+    assert side.sum() > 0 and side.sum() < wall.sum()
+    KD = imex.assemble_K_walls(d, wall)
+    A = KD.toarray()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).max() < 0.0
+    lin = lambda q: 0.3 + 1.7 * q[..., 0] - 0.9 * q[..., 1]
+    u = lin(d.main_node_xy()).reshape(-1)
+    gb = imex.dirichlet_rhs(d, wall, lin).reshape(-1)
+    assert np.abs(KD @ u + gb).max() <= 1e-12 * np.abs(gb).max()
+    lx = lambda q: 0.25 - 0.5 * q[..., 0]
+    KS = imex.assemble_K_walls(d, side)
+    ux = lx(d.main_node_xy()).reshape(-1)
+    gs = imex.dirichlet_rhs(d, side, lx).reshape(-1)
+    assert np.abs(KS @ ux + gs).max() <= 1e-12 * np.abs(gs).max()
+    if p >= 2:
+        quad = lambda q: q[..., 0] ** 2 + q[..., 1] ** 2
+        uq = quad(d.main_node_xy()).reshape(-1)
+        gq = imex.dirichlet_rhs(d, wall, quad).reshape(-1)
+        want = 4.0 * d.main_weights().reshape(-1)
+        assert np.abs(KD @ uq + gq - want).max() <= 1e-12 * np.abs(want).max()
+    KN = imex.assemble_K_walls(d, None).toarray()
+    ev = np.linalg.eigvalsh(0.5 * (KN + KN.T))
+    assert abs(ev[-1]) <= 1e-12 * abs(ev[0]) and ev[-2] < 0.0
+    assert np.abs(KN @ np.ones(KN.shape[0])).max() <= 1e-12 * np.abs(KN).max()
+
+
+def test_dirichlet_diffusion_keeps_the_linear_steady_state():
+    """The implicit diffusion step with Dirichlet side walls leaves the conduction profile
+    u = 0.5 - x unchanged (it is the steady state), for any time step."""
+    d = _disc(6, 2, periodic=False, seed=14)
+    _, side = _wall_side_masks(d)
+    prof = lambda q: 0.5 - q[..., 0]
+    KS = imex.assemble_K_walls(d, side)
+    gb = imex.dirichlet_rhs(d, side, prof)
+    u = prof(d.main_node_xy())[:, None, :]
+    for c in (1e-3, 0.1, 10.0):
+        out = imex.diffusion_solve(d, KS, u, c, gb)
+        assert np.abs(out - u).max() <= 1e-11
