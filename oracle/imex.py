@@ -127,7 +127,9 @@ def dual_to_main(disc: OracleDisc, vd: np.ndarray) -> np.ndarray:
 #     projected gradient is grad u_l itself (a polynomial of the half's space):
 #       -int_{T_lj} grad phi_k . grad phi_l.
 # The Laplacian is L(u) = K_W u + G_b, with K_W = K plus these wall cells and
-# G_b = sum_j D_lj Mhat_j^{-1} int_Gamma psi u_b n ds over the Dirichlet edges.
+# G_b = sum_j D_lj Mhat_j^{-1} int_Gamma psi u_b n ds over the Dirichlet edges.  The data enter
+# as their nodal interpolant of degree p along each wall edge (values at the p+1 equispaced
+# edge nodes), as every field of the nodal scheme does.
 
 
 def _wall_edges(disc: OracleDisc, mask) -> np.ndarray:
@@ -184,7 +186,8 @@ def assemble_K_walls(disc: OracleDisc, dirichlet_mask=None) -> sp.csr_matrix:
 
 
 def dirichlet_rhs(disc: OracleDisc, dirichlet_mask, trace) -> np.ndarray:
-    """G_b [ne, Nphi] for the data trace(xy [..., 2]) -> [...] on the masked wall edges."""
+    """G_b [ne, Nphi] for the data trace(xy [..., 2]) -> [...] on the masked wall edges (taken
+    through its values at the edge nodes)."""
     m = disc.mesh
     out = np.zeros((m.ne, disc.nphi))
     J = _wall_edges(disc, dirichlet_mask)
@@ -200,7 +203,15 @@ def dirichlet_rhs(disc: OracleDisc, dirichlet_mask, trace) -> np.ndarray:
     xe = A[:, None] + t[None, :, None] * (B - A)[:, None]      # [E, q, 2]
     psi_e = basis.psi(p, np.broadcast_to(1.0 - t, (J.size, t.size)),
                       np.broadcast_to(t, (J.size, t.size)))[:, :, h]  # [E, q, nh]
-    ub = trace(xe)                                              # [E, q]
+    # the data's degree-p interpolant through the p+1 equispaced nodes of the edge
+    tn = np.arange(p + 1) / p
+    xn = A[:, None] + tn[None, :, None] * (B - A)[:, None]       # [E, p+1, 2]
+    lag = np.ones((t.size, p + 1))
+    for a in range(p + 1):
+        for b in range(p + 1):
+            if b != a:
+                lag[:, a] *= (t - tn[b]) / (tn[a] - tn[b])
+    ub = trace(xn) @ lag.T                                      # [E, q]
     line = np.einsum("q,e,eqk,eq,ec->ekc", wt, m.edge_len[J], psi_e, ub, m.normal[J])
     g = np.linalg.solve(Mh[:, None], line.transpose(0, 2, 1)[..., None])[..., 0]  # [E, 2, nh]
     np.add.at(out, m.left[J], np.einsum("ekmc,ecm->ek", Dl, g))
