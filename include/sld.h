@@ -225,14 +225,21 @@ sld_status sld_cg_solve(sld_disc disc, const double* b, double* p, const sld_cg_
 sld_status sld_dual_to_main(sld_disc disc, const double* v, int32_t nc, double* out, void* stream);
 sld_status sld_main_to_dual(sld_disc disc, const double* v, int32_t nc, double* out, void* stream);
 
-/* Viscous (implicit diffusion) solve of the IMEX stages, the advection-diffusion scheme of
- * eq. ad5 with the main-grid Laplacian K of eq. pressure_final:
- *   (Mbar - c K) x = Mbar f,   c = a_ss dt nu >= 0   (c = 0: x = f)
+/* Viscous / thermal (implicit diffusion) solve of the IMEX stages, the advection-diffusion
+ * scheme of eq. ad5 with the main-grid Laplacian built from the staggered gradient and
+ * divergence (eq. pressure_final) plus wall cells:
+ *   (Mbar - c K_W) x = Mbar f + c G_b,   c = a_ss dt (viscosity or diffusivity) >= 0
+ * (c = 0: x = f).  On a wall edge the dual cell is the left half alone.  Edges flagged in
+ * wall_dirichlet (device uint8 [nd], caller's edge numbering; NULL: none) are Dirichlet: the
+ * cell's gradient takes the jump to the data wall_values (device float64 [nd][p+1], the values
+ * at the edge's p+1 nodes counted from its first vertex A; NULL: zero data), which enter G_b.
+ * The other wall edges have zero flux (the cell keeps its sub-triangle stiffness, no jump).
  * f, x device float64 [ne][N_phi] (may alias).  Conjugate gradients on the positive definite
- * (1/c) Mbar - K, warm-started from f, with the iteration kernel of sld_cg_solve; params as
+ * (1/c) Mbar - K_W, warm-started from f, with the iteration kernel of sld_cg_solve; params as
  * there (precision must be 0: FP64; warm_start is ignored); the stopping rule is relative to
- * ||(1/c) Mbar f||.  Blocks like sld_cg_solve.  SLD_E_NOCONV / SLD_E_BREAKDOWN as there. */
-sld_status sld_viscous_solve(sld_disc disc, const double* f, double c, double* x,
+ * ||(1/c) Mbar f + G_b||.  Blocks like sld_cg_solve.  SLD_E_NOCONV / SLD_E_BREAKDOWN as there. */
+sld_status sld_viscous_solve(sld_disc disc, const double* f, double c,
+                             const uint8_t* wall_dirichlet, const double* wall_values, double* x,
                              const sld_cg_params* params, sld_cg_report* report, void* stream);
 
 /* sld_state: the device workspace of sld_imex_step on one disc (velocity on the main grid,

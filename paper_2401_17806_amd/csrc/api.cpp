@@ -201,6 +201,7 @@ void free_disc(sld_disc_s* d) {
     dfree(d->ops32_dev);
     dfree(d->sl_dev);
     dfree(w.scal);
+    dfree(w.wall_i);
     if (w.graph) (void)hipGraphExecDestroy(w.graph);
     if (w.graph_shift) (void)hipGraphExecDestroy(w.graph_shift);
     if (w.capture) (void)hipStreamDestroy(w.capture);
@@ -595,6 +596,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     if (e == hipSuccess) e = dalloc(&w.part, size_t(8) * G);
     if (e == hipSuccess) e = dalloc(&w.part_s, size_t(2) * G);
     if (e == hipSuccess) e = dalloc(&w.scal, CgScalars::NSCAL);
+    if (e == hipSuccess) e = dalloc(&w.wall_i, size_t(m->ne));
     for (int k = 0; k < 2; ++k) {
         if (e == hipSuccess) e = dalloc(&w.r32[k], nv);
         if (e == hipSuccess) e = dalloc(&w.q32[k], nv);
@@ -608,6 +610,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         up.copy(d->ops32_dev, h32.data(), h32.size());
         up.copy(d->sl_dev, hsl.data(), hsl.size());
         up.zero(w.scal, CgScalars::NSCAL * sizeof(double));
+        up.zero(w.wall_i, size_t(m->ne));
         up.zero(w.scal_in, CgScalars::NSCAL * sizeof(double));
         e = up.finish();
     }
@@ -1084,13 +1087,18 @@ void free_state(sld_state_s* st) {
     delete st;
 }
 
-// (Mbar - c K) x = Mbar f for one [ne][N] field (f read through strides); x [ne][N].
+// (Mbar - c K_W) x = Mbar f + c G_b for one [ne][N] field (f read through strides); x [ne][N].
+// K_W: the diffusion operator, with Dirichlet cells on the wall edges flagged in `mask` (device
+// [nd], NULL none) and zero-flux cells on the other walls; gb: G_b of the data or NULL.
 sld_status viscous_field(sld_disc d, const double* f, int64_t f_is, int64_t f_cs, int comp,
-                         double c, double* x, double* bbuf, const sld_cg_params* prm,
-                         sld_cg_report* rep, hipStream_t s) {
+                         double c, const unsigned char* mask, const double* gb, double* x,
+                         double* bbuf, const sld_cg_params* prm, sld_cg_report* rep,
+                         hipStream_t s) {
     const double sigma = 1.0 / c;
-    // b = -sigma Mbar f (the CG runs -(K - sigma Mbar) x = -b); x = f is the initial guess
-    SLD_HIP_CHECK(launch_mass_rhs(d, f, f_is, f_cs, comp, -sigma, bbuf, x, s));
+    SLD_HIP_CHECK(launch_wall_mask(d, mask, s));
+    // b = -sigma Mbar f - G_b (the CG runs -(K_W - sigma Mbar) x = -b); x = f is the initial
+    // guess
+    SLD_HIP_CHECK(launch_mass_rhs(d, f, f_is, f_cs, comp, -sigma, gb, -1.0, bbuf, x, s));
     sld_cg_params q = *prm;
     q.warm_start = 1;
     return cg_solve_impl(d, bbuf, x, &q, rep, s, sigma);
@@ -1122,7 +1130,8 @@ sld_status sld_main_to_dual(sld_disc d, const double* v, int32_t nc, double* out
     return SLD_OK;
 }
 
-sld_status sld_viscous_solve(sld_disc d, const double* f, double c, double* x,
+sld_status sld_viscous_solve(sld_disc d, const double* f, double c,
+                             const uint8_t* wall_dirichlet, const double* wall_values, double* x,
                              const sld_cg_params* prm, sld_cg_report* rep, void* stream) {
     SLD_REQUIRE(d && f && x && prm, SLD_E_INVALID, "sld_viscous_solve: NULL argument");
     SLD_REQUIRE(std::isfinite(c) && c >= 0.0, SLD_E_INVALID,
@@ -1141,9 +1150,14 @@ sld_status sld_viscous_solve(sld_disc d, const double* f, double c, double* x,
         }
         return SLD_OK;
     }
-    // the caller-order right-hand side lives in the CG's second residual buffer, which the
-    // setup does not touch before it has gathered b
-    return viscous_field(d, f, d->nphi, 0, 0, c, x, d->cg.r[1], prm, rep, s);
+    // the caller-order right-hand side lives in the CG's second residual buffer and G_b in its
+    // second q buffer: the setup touches neither before it has gathered b
+    const double* gb = nullptr;
+    if (wall_dirichlet && wall_values) {
+        SLD_HIP_CHECK(launch_dirichlet_rhs(d, wall_dirichlet, wall_values, d->cg.q[1], s));
+        gb = d->cg.q[1];
+    }
+    return viscous_field(d, f, d->nphi, 0, 0, c, wall_dirichlet, gb, x, d->cg.r[1], prm, rep, s);
 }
 
 sld_status sld_state_create(sld_disc d, sld_state* out) {
@@ -1210,8 +1224,8 @@ sld_status sld_imex_step(sld_state st, const sld_imex_params* prm, double dt, do
     const double c = a_ss * dt * prm->nu;
     if (c > 0.0) {
         for (int comp = 0; comp < 2; ++comp) {
-            sld_status e = viscous_field(d, st->vfoot, 2 * N, N, comp, c, st->vsbar + comp * ne * N,
-                                         st->b, &prm->viscous, &r->viscous[comp], s);
+            sld_status e = viscous_field(d, st->vfoot, 2 * N, N, comp, c, nullptr, nullptr,
+                                         st->vsbar + comp * ne * N, st->b, &prm->viscous, &r->viscous[comp], s);
             if (e != SLD_OK) return done(e);
         }
         SLD_HIP_CHECK(launch_main_to_dual(d, st->vsbar, 2, N, ne * N, st->vs, s));

@@ -32,6 +32,17 @@
 
 namespace sld_dev {
 
+// Treatment of a wall edge (neighbour code < 0) in the operator cores.
+//   kWallAbsent:   the pressure operator of eq. pressure_final: wall dual cells carry
+//                  prescribed velocity and take no part (the sub-triangle's share of the volume
+//                  term is given back).
+//   kWallDirichlet: diffusion solves: the wall cell's gradient takes the jump to the boundary
+//                  data, here zero (the data enter the right-hand side): the interior-edge form
+//                  with a neighbour of zero area whose trace is zero.
+//   kWallFlux:     diffusion solves, zero flux: the wall cell keeps its sub-triangle stiffness
+//                  (the full-triangle volume term stands) and adds nothing.
+enum WallKind { kWallAbsent = 0, kWallDirichlet = 1, kWallFlux = 2 };
+
 constexpr int kBlockTri = 3 * kTriPerBlock;      // 192 threads: three lanes per triangle
 constexpr int kBlockFlat = 256;                  // threads of flat (per-DOF) kernels
 constexpr int kBlockCG = 4 * kTriPerBlock;       // 256 threads: CG iteration, one wave per role
@@ -131,7 +142,8 @@ template <int P, class Ops, typename Real>
 __device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, int nb, int ar,
                                                double4 er, const Real (&pl)[RefOps<P>::NPHI],
                                                const Real (&pr)[RefOps<P>::NPHI],
-                                               Real (&y)[RefOps<P>::NPHI]) {
+                                               Real (&y)[RefOps<P>::NPHI],
+                                               int wall = kWallAbsent) {
     constexpr int N = RefOps<P>::NPHI;
     constexpr int NE = P + 1;
     constexpr Tab<P> T{};
@@ -170,7 +182,9 @@ __device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, 
         y[k] = -g.A * (m00 * s0 + m01 * s1 + m11 * s2);
     }
     const Real snx = (Real)e1y, sny = (Real)(-e1x);  // |Gamma| n, outward, of local edge 0
-    if (nb < 0) {
+    const bool ghost = nb < 0 && wall == kWallDirichlet;
+    if (nb < 0 && wall == kWallFlux) return;
+    if (nb < 0 && !ghost) {
         // wall edge: no dual coupling; give back this sub-triangle's share of the volume term
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -187,12 +201,13 @@ __device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, 
     }
     double f1x, f1y, f2x, f2y;
     relabel(er, ar, f1x, f1y, f2x, f2y);
-    const Geo grd = make_geo(f1x, f1y, f2x, f2y);
+    // a Dirichlet wall is an edge to a ghost neighbour of zero area and zero trace
+    Geo grd = ghost ? Geo{0.0, 0.0, 0.0, 0.0, 0.0} : make_geo(f1x, f1y, f2x, f2y);
     const GeoR<Real> gr(grd);
     const Real wsum = (Real)(1.0 / (gd.A + grd.A));
     Real delta[NE];
 #pragma unroll
-    for (int m = 0; m < NE; ++m) delta[m] = pr[P - m] - pl[m];  // edge-0 nodes are 0..P
+    for (int m = 0; m < NE; ++m) delta[m] = (ghost ? Real(0) : pr[P - m]) - pl[m];  // edge-0 nodes are 0..P
     Real gd0[NE], gd1[NE], tn[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
@@ -274,14 +289,17 @@ template <int P, int AL, class Ops, typename Real>
 __device__ __forceinline__ void edge_wave_core(const Ops& R, double4 e, int nb, int ar, double4 er,
                                                const Real (&pl)[RefOps<P>::NPHI],
                                                const Real (&pr)[RefOps<P>::NPHI],
-                                               Real (&y)[RefOps<P>::NPHI]) {
+                                               Real (&y)[RefOps<P>::NPHI],
+                                               int wall = kWallAbsent) {
     constexpr int N = RefOps<P>::NPHI;
     constexpr int NE = P + 1;
     const Geo gd = make_geo(e.x, e.y, e.z, e.w);
     const GeoR<Real> g(gd);
 #pragma unroll
     for (int k = 0; k < N; ++k) y[k] = Real(0);
-    if (nb < 0) {
+    const bool ghost = nb < 0 && wall == kWallDirichlet;
+    if (nb < 0 && wall == kWallFlux) return;
+    if (nb < 0 && !ghost) {
         const Real m00 = (Real)(gd.G00 * gd.G00 + gd.G01 * gd.G01);
         const Real m01 = (Real)(gd.G00 * gd.G10 + gd.G01 * gd.G11);
         const Real m11 = (Real)(gd.G10 * gd.G10 + gd.G11 * gd.G11);
@@ -304,12 +322,14 @@ __device__ __forceinline__ void edge_wave_core(const Ops& R, double4 e, int nb, 
     const Real snx = (Real)ey, sny = (Real)(-ex);
     double f1x, f1y, f2x, f2y;
     relabel(er, ar, f1x, f1y, f2x, f2y);
-    const Geo grd = make_geo(f1x, f1y, f2x, f2y);
+    // a Dirichlet wall is an edge to a ghost neighbour of zero area and zero trace
+    Geo grd = ghost ? Geo{0.0, 0.0, 0.0, 0.0, 0.0} : make_geo(f1x, f1y, f2x, f2y);
     const GeoR<Real> gr(grd);
     const Real wsum = (Real)(1.0 / (gd.A + grd.A));
     Real delta[NE];
 #pragma unroll
-    for (int m = 0; m < NE; ++m) delta[m] = pr[P - m] - pl[edge_node(P, AL, m)];
+    for (int m = 0; m < NE; ++m)
+        delta[m] = (ghost ? Real(0) : pr[P - m]) - pl[edge_node(P, AL, m)];
     Real gd0[NE], gd1[NE], tn[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
@@ -360,7 +380,8 @@ __device__ __forceinline__ void schur_edge_lane(int64_t i, int al, const RefOps<
                                                 const double4* __restrict__ geo,
                                                 const int4* __restrict__ nbr, const L& ld,
                                                 double (&pl)[RefOps<P>::NPHI],
-                                                double (&y)[RefOps<P>::NPHI]) {
+                                                double (&y)[RefOps<P>::NPHI],
+                                                int wall = kWallAbsent) {
     constexpr int N = RefOps<P>::NPHI;
 #pragma unroll
     for (int l = 0; l < N; ++l) pl[l] = ld.at(i, rot_sel<P>(al, l));
@@ -378,7 +399,7 @@ __device__ __forceinline__ void schur_edge_lane(int64_t i, int al, const RefOps<
 #pragma unroll
         for (int l = 0; l < N; ++l) pr[l] = 0.0;
     }
-    edge_lane_core<P>(al, R, geo[i], nb, ar, er, pl, pr, y);
+    edge_lane_core<P>(al, R, geo[i], nb, ar, er, pl, pr, y, wall);
 }
 
 // Scatter a lane's local rows to LDS slot al in natural numbering.

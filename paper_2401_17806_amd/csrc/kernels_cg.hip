@@ -51,6 +51,15 @@ __device__ __forceinline__ double shifted_row(const RefOps<P>& R, const double4*
     return fma(-sigma * A, s, kx);
 }
 
+// Wall treatment of local edge al of internal triangle i: the pressure operator has no wall
+// cells; the mass-shifted (diffusion) system has Dirichlet or zero-flux wall cells, the
+// Dirichlet edges flagged in wall_i (bit al).
+__device__ __forceinline__ int wall_kind(bool diffusion, const unsigned char* __restrict__ wall_i,
+                                         int64_t i, int al) {
+    if (!diffusion) return kWallAbsent;
+    return (wall_i != nullptr && ((wall_i[i] >> al) & 1)) ? kWallDirichlet : kWallFlux;
+}
+
 // r = K x - b_int (true residual of the CG system -K x = -b_int) and its rr partials.
 template <int P>
 __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restrict__ ops,
@@ -61,7 +70,8 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
                                                         double* __restrict__ r,
                                                         double* __restrict__ part_out,
                                                         const double* __restrict__ scal,
-                                                        double sigma) {
+                                                        double sigma,
+                                                        const unsigned char* __restrict__ wall_i) {
     constexpr int N = RefOps<P>::NPHI;
     if (scal[S::DONE] != 0.0) return;
     __shared__ double sm[kTriPerBlock][4][N];
@@ -73,7 +83,8 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
         if (valid) {
             double pl[N], y[N];
             LoadPlain<N> ld{x};
-            schur_edge_lane<P>(i, al, *ops, geo, nbr, ld, pl, y);
+            schur_edge_lane<P>(i, al, *ops, geo, nbr, ld, pl, y,
+                               wall_kind(sigma != 0.0, wall_i, i, al));
             lds_scatter<P>(&sm[tl][0][0], al, y);
         }
         __syncthreads();
@@ -130,7 +141,9 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
                                                        const double4* __restrict__ geo,
                                                        const int4* __restrict__ nbr,
                                                        const int* __restrict__ halo_pad, int hmax,
-                                                       int64_t ne, Real* __restrict__ x,
+                                                       int64_t ne,
+                                                       const unsigned char* __restrict__ wall_i,
+                                                       Real* __restrict__ x,
                                                        const Real* __restrict__ r_in,
                                                        const Real* __restrict__ q_in,
                                                        const Real* __restrict__ d_in,
@@ -350,9 +363,10 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
 #pragma unroll
                         for (int l = 0; l < N; ++l) pr[l] = Real(0);
                     }
-                    if (role == 0) edge_wave_core<P, 0, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y);
-                    else if (role == 1) edge_wave_core<P, 1, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y);
-                    else edge_wave_core<P, 2, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y);
+                    const int wk = wall_kind(kShift, wall_i, i, role);
+                    if (role == 0) edge_wave_core<P, 0, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y, wk);
+                    else if (role == 1) edge_wave_core<P, 1, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y, wk);
+                    else edge_wave_core<P, 2, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y, wk);
                 }
 #pragma unroll
                 for (int k = 0; k < N; ++k) sm[(lane * 4 + role) * N + k] = y[k];
@@ -381,7 +395,8 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
                     for (int l = 0; l < N; ++l) pr[l] = Real(0);
                 }
                 const double4 ei = geo[i];
-                edge_lane_core<P, Ops, Real>(al, *ops, ei, nb, ar, er, pl, pr, y);
+                edge_lane_core<P, Ops, Real>(al, *ops, ei, nb, ar, er, pl, pr, y,
+                                             wall_kind(kShift, wall_i, i, al));
                 if constexpr (kShift) {
                     // this lane's rows (rotation-orbit representatives, the centre on lane 0);
                     // Mref is invariant under the relabelling
@@ -423,6 +438,26 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
 }
 
 // ---------------------------------------------------------------- setup and finish
+// wall_i[i] (internal order): bit al set when local edge al of the triangle is a wall edge
+// flagged Dirichlet in edge_mask [nd] (caller's edge numbering; NULL: none)
+__global__ __launch_bounds__(kBlockFlat) void k_wall_mask(int64_t ne, const int* __restrict__ perm,
+                                                          const int4* __restrict__ nbr,
+                                                          const int4* __restrict__ tedges,
+                                                          const unsigned char* __restrict__ edge_mask,
+                                                          unsigned char* __restrict__ wall_i) {
+    const int64_t i = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x;
+    if (i >= ne) return;
+    const int t = perm[i];
+    const int4 nb = nbr[t], te = tedges[t];
+    unsigned char bits = 0;
+    if (edge_mask) {
+        if (nb.x < 0 && edge_mask[te.x >> 1]) bits |= 1;
+        if (nb.y < 0 && edge_mask[te.y >> 1]) bits |= 2;
+        if (nb.z < 0 && edge_mask[te.z >> 1]) bits |= 4;
+    }
+    wall_i[i] = bits;
+}
+
 // partials of sum(b)
 __global__ __launch_bounds__(kBlockFlat) void k_sum_partials(const double* __restrict__ b, int64_t n,
                                                              double* __restrict__ part) {
@@ -553,7 +588,8 @@ __global__ __launch_bounds__(kBlockTri) void k_apply_internal(const RefOps<P>* _
                                                               int64_t ne,
                                                               const double* __restrict__ p,
                                                               double* __restrict__ out,
-                                                              double sigma) {
+                                                              double sigma,
+                                                              const unsigned char* __restrict__ wall_i) {
     constexpr int N = RefOps<P>::NPHI;
     __shared__ double sm[kTriPerBlock][4][N];
     const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
@@ -562,7 +598,7 @@ __global__ __launch_bounds__(kBlockTri) void k_apply_internal(const RefOps<P>* _
     if (valid) {
         double pl[N], y[N];
         LoadPlain<N> ld{p};
-        schur_edge_lane<P>(i, al, *ops, geo, nbr, ld, pl, y);
+        schur_edge_lane<P>(i, al, *ops, geo, nbr, ld, pl, y, wall_kind(sigma != 0.0, wall_i, i, al));
         lds_scatter<P>(&sm[tl][0][0], al, y);
     }
     __syncthreads();
@@ -701,7 +737,7 @@ hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p
     // r_0 = K x - b_int (the residual of -K x = -b_int); q, d of "iteration -1" are zero
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(G), dim3(kBlockTri), 0, s,
                                           ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
-                                          w.r[0], w.part_s, w.scal, sigma));
+                                          w.r[0], w.part_s, w.scal, sigma, w.wall_i));
     return hipGetLastError();
 }
 
@@ -727,7 +763,7 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F, SH, ST>), dim3(G), \
                                           dim3(F ? kBlockCG : kBlockTri), lds, s, ops_of<PP>(d), \
                                           m->geo_i,                                             \
-                                          m->nbr_i, m->halo_pad, m->hmax, m->ne, w.x,           \
+                                          m->nbr_i, m->halo_pad, m->hmax, m->ne, w.wall_i, w.x, \
                                           w.r[parity], w.q[parity], w.d[parity], w.r[o],        \
                                           w.q[o], w.d[o], w.part + parity * 4 * G,              \
                                           w.part + o * 4 * G, w.scal, parity))
@@ -788,6 +824,14 @@ int cg_grid_for(const sld_disc_s* d, bool* front) {
     return (int)((g + 7) & ~int64_t(7));
 }
 
+hipError_t launch_wall_mask(const sld_disc_s* d, const unsigned char* edge_mask, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    hipLaunchKernelGGL(k_wall_mask, dim3((unsigned)((m->ne + kBlockFlat - 1) / kBlockFlat)),
+                       dim3(kBlockFlat), 0, s, m->ne, m->perm, m->nbr, m->tedges, edge_mask,
+                       d->cg.wall_i);
+    return hipGetLastError();
+}
+
 hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     const CgWork& w = d->cg;
@@ -795,7 +839,7 @@ hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hi
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_apply_internal<PP>,
                                           dim3((unsigned)((m->ne + kTriPerBlock - 1) / kTriPerBlock)),
                                           dim3(kBlockTri), 0, s, ops_of<PP>(d), m->geo_i, m->nbr_i,
-                                          m->ne, w.x, w.q[0], sigma));
+                                          m->ne, w.x, w.q[0], sigma, w.wall_i));
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_finish_partials<PP>, dim3(G), dim3(kBlockFlat), 0, s,
                                           ops_of<PP>(d), m->geo_i, m->ne, w.q[0], w.b, w.x,
                                           w.part_s));
@@ -820,7 +864,7 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>, F, false, ST>), dim3(G), \
                                           dim3(F ? kBlockCG : kBlockTri), lds, s, ops32_of<PP>(d), \
                                           m->geo_i,                                             \
-                                          m->nbr_i, m->halo_pad, m->hmax, m->ne, w.e32,         \
+                                          m->nbr_i, m->halo_pad, m->hmax, m->ne, w.wall_i, w.e32, \
                                           w.r32[parity], w.q32[parity], w.d32[parity],          \
                                           w.r32[o], w.q32[o], w.d32[o],                         \
                                           w.part32 + parity * 4 * G, w.part32 + o * 4 * G,      \
@@ -856,7 +900,7 @@ hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s) {
     hipLaunchKernelGGL(k_rel_accumulate, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.x, w.e32, w.scal);
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(w.grid), dim3(kBlockTri), 0, s,
                                           ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
-                                          w.r[0], w.part_s, w.scal, 0.0));
+                                          w.r[0], w.part_s, w.scal, 0.0, w.wall_i));
     hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal,
                        (int)S::RR, 1.0);
     hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],

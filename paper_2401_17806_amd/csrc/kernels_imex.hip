@@ -159,13 +159,14 @@ __global__ __launch_bounds__(kBlockX) void k_main_to_dual(const RefOps<P>* __res
     }
 }
 
-// b[i][k] = scale * A_i (Mref f_i)_k and x0[i][l] = f_i,l for component c of f (element (i, c, l)
-// at f[i * f_is + c * f_cs + l]); b and x0 are [ne][Nphi].
+// b[i][k] = scale * A_i (Mref f_i)_k + gcoef * gb[i][k] and x0[i][l] = f_i,l for component c of
+// f (element (i, c, l) at f[i * f_is + c * f_cs + l]); b, gb and x0 are [ne][Nphi].
 template <int P>
 __global__ __launch_bounds__(kBlockX) void k_mass_rhs(const RefOps<P>* __restrict__ ops,
                                                      const double4* __restrict__ geo, int64_t ne,
                                                      const double* __restrict__ f, int64_t f_is,
                                                      int64_t f_cs, int c, double scale,
+                                                     const double* __restrict__ gb, double gcoef,
                                                      double* __restrict__ b, double* __restrict__ x0) {
     constexpr int N = RefOps<P>::NPHI;
     const RefOps<P>& R = *ops;
@@ -182,9 +183,77 @@ __global__ __launch_bounds__(kBlockX) void k_mass_rhs(const RefOps<P>* __restric
         double s = 0.0;
 #pragma unroll
         for (int l = 0; l < N; ++l) s = fma(R.Mref[k][l], v[l], s);
-        b[i * N + k] = scale * A * s;
+        b[i * N + k] = scale * A * s + (gb ? gcoef * gb[i * N + k] : 0.0);
         if (x0) x0[i * N + k] = v[k];
     }
+}
+
+// G_b of Dirichlet data on wall edges: for each triangle, the diffusion operator's wall-cell
+// terms with the triangle's own field zero and the data u_b (at the p+1 edge nodes, counted
+// from v_alpha) as the ghost trace -- the interior-edge form with a neighbour of zero area:
+// on the edge nodes x_H = 3 |Gamma| n (C u_b) / A, then the line term |Gamma| M1 (n . x_H) and
+// the sub-triangle correction -A sum_d Pt_alpha,d (G x_H)_d.
+template <int P>
+__global__ __launch_bounds__(kBlockX) void k_dirichlet_rhs(const RefOps<P>* __restrict__ ops,
+                                                          const double4* __restrict__ geo,
+                                                          const int4* __restrict__ nbr,
+                                                          const int4* __restrict__ tedges, int64_t ne,
+                                                          const unsigned char* __restrict__ mask,
+                                                          const double* __restrict__ values,
+                                                          double* __restrict__ out) {
+    constexpr int N = RefOps<P>::NPHI;
+    constexpr int NE = P + 1;
+    const RefOps<P>& R = *ops;
+    const int64_t i = (int64_t)blockIdx.x * kBlockX + threadIdx.x;
+    if (i >= ne) return;
+    const double4 e = geo[i];
+    const Geo g = make_geo(e.x, e.y, e.z, e.w);
+    const int4 nb4 = nbr[i], te4 = tedges[i];
+    double y[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) y[k] = 0.0;
+    for (int al = 0; al < 3; ++al) {
+        const int nb = al == 0 ? nb4.x : (al == 1 ? nb4.y : nb4.z);
+        if (nb >= 0) continue;
+        const int64_t j = (al == 0 ? te4.x : (al == 1 ? te4.y : te4.z)) >> 1;
+        if (!mask[j]) continue;
+        double ex, ey;
+        if (al == 0) { ex = e.x; ey = e.y; }
+        else if (al == 1) { ex = e.z - e.x; ey = e.w - e.y; }
+        else { ex = -e.z; ey = -e.w; }
+        const double snx = ey, sny = -ex;
+        const double* ub = values + j * NE;
+        double tn[NE], gd0[NE], gd1[NE];
+#pragma unroll
+        for (int m = 0; m < NE; ++m) {
+            double cd = 0.0;
+#pragma unroll
+            for (int q = 0; q < NE; ++q) cd = fma(R.C[m][q], ub[q], cd);
+            const double hx = 3.0 * snx * cd / g.A, hy = 3.0 * sny * cd / g.A;
+            tn[m] = snx * hx + sny * hy;
+            gd0[m] = g.G00 * hx + g.G01 * hy;
+            gd1[m] = g.G10 * hx + g.G11 * hy;
+        }
+#pragma unroll
+        for (int m = 0; m < NE; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NE; ++q) s = fma(R.M1[m][q], tn[q], s);
+            y[edge_node(P, al, m)] += s;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < NE; ++m) {
+                s = fma(R.Pt[al][0][k][m], gd0[m], s);
+                s = fma(R.Pt[al][1][k][m], gd1[m], s);
+            }
+            y[k] = fma(-g.A, s, y[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) out[i * N + k] = y[k];
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlockX - 1) / kBlockX); }
@@ -222,10 +291,20 @@ hipError_t launch_main_to_dual(const sld_disc_s* d, const double* vm, int nc, in
 }
 
 hipError_t launch_mass_rhs(const sld_disc_s* d, const double* f, int64_t f_is, int64_t f_cs, int c,
-                           double scale, double* b, double* x0, hipStream_t s) {
+                           double scale, const double* gb, double gcoef, double* b, double* x0,
+                           hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_mass_rhs<PP>, dim3(nblk(m->ne)), dim3(kBlockX), 0, s,
-                                          ops_of<PP>(d), m->geo, m->ne, f, f_is, f_cs, c, scale, b,
-                                          x0));
+                                          ops_of<PP>(d), m->geo, m->ne, f, f_is, f_cs, c, scale, gb,
+                                          gcoef, b, x0));
+    return hipGetLastError();
+}
+
+hipError_t launch_dirichlet_rhs(const sld_disc_s* d, const unsigned char* edge_mask,
+                                const double* values, double* out, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_dirichlet_rhs<PP>, dim3(nblk(m->ne)), dim3(kBlockX), 0,
+                                          s, ops_of<PP>(d), m->geo, m->nbr, m->tedges, m->ne,
+                                          edge_mask, values, out));
     return hipGetLastError();
 }

@@ -74,6 +74,8 @@ struct CgWork {
     int grid = 0;                  // blocks of every CG kernel
     bool front = false;            // iteration kernel variant: one tile per block, four roles
     int stream_x = -1;             // x with non-temporal accesses: -1 by working-set size, 0/1
+    unsigned char* wall_i = nullptr;  // [ne] internal order: Dirichlet wall edges (bit per local
+                                      // edge) of the current diffusion solve
     std::vector<hipEvent_t> events;  // profiling events (created on first profiled solve)
     // mixed precision: FP32 inner CG state (e32 = the correction), its partials and scalars
     float* r32[2] = {nullptr, nullptr};
@@ -127,6 +129,8 @@ hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p
                            double rtol, int maxit, double sigma, hipStream_t s);
 hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream_t s);
 hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hipStream_t s);
+// Dirichlet wall flags of the next diffusion solve from a per-edge mask (device [nd], NULL none)
+hipError_t launch_wall_mask(const sld_disc_s* d, const unsigned char* edge_mask, hipStream_t s);
 hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s);
 hipError_t launch_rel_init(const sld_disc_s* d, double rtol, int maxit, hipStream_t s);
 hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s);
@@ -139,5 +143,10 @@ hipError_t launch_dual_to_main(const sld_disc_s* d, const double* vd, int nc, do
                                int64_t o_is, int64_t o_cs, hipStream_t s);
 hipError_t launch_main_to_dual(const sld_disc_s* d, const double* vm, int nc, int64_t v_is,
                                int64_t v_cs, double* out, hipStream_t s);
+// b = scale A_i Mref f_c + gcoef gb (gb [ne][N] or NULL); x0 = f_c (or NULL)
 hipError_t launch_mass_rhs(const sld_disc_s* d, const double* f, int64_t f_is, int64_t f_cs, int c,
-                           double scale, double* b, double* x0, hipStream_t s);
+                           double scale, const double* gb, double gcoef, double* b, double* x0,
+                           hipStream_t s);
+// G_b [ne][N] of Dirichlet data on the flagged wall edges (mask and values [nd][p+1] device)
+hipError_t launch_dirichlet_rhs(const sld_disc_s* d, const unsigned char* edge_mask,
+                                const double* values, double* out, hipStream_t s);

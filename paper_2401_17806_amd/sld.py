@@ -88,8 +88,8 @@ _sig("sld_ref_operator", [_vp, _i32, _i32, _c_dp, _i64, ctypes.POINTER(_i64)])
 _sig("sld_sl_advect", [_vp, _vp, _vp, _i32, ctypes.c_double, _vp, _vp])
 _sig("sld_dual_to_main", [_vp, _vp, _i32, _vp, _vp])
 _sig("sld_main_to_dual", [_vp, _vp, _i32, _vp, _vp])
-_sig("sld_viscous_solve", [_vp, _vp, ctypes.c_double, _vp, ctypes.POINTER(sld_cg_params),
-                           ctypes.POINTER(sld_cg_report), _vp])
+_sig("sld_viscous_solve", [_vp, _vp, ctypes.c_double, _vp, _vp, _vp,
+                           ctypes.POINTER(sld_cg_params), ctypes.POINTER(sld_cg_report), _vp])
 _sig("sld_state_create", [_vp, ctypes.POINTER(_vp)])
 _sig("sld_state_destroy", [_vp], None)
 _sig("sld_imex_step", [_vp, ctypes.POINTER(sld_imex_params), ctypes.c_double, _vp, _vp,
@@ -386,15 +386,27 @@ class Disc:
                                      self._dev(out, shape, "out"), self._stream(stream)))
         return out
 
-    def sld_viscous_solve(self, f, c, x=None, rtol=1e-12, maxit=100000, graph_block=32,
-                          stream=None):
-        """x with (Mbar - c K) x = Mbar f (FP64 CG)."""
+    def sld_viscous_solve(self, f, c, x=None, wall_dirichlet=None, wall_values=None, rtol=1e-12,
+                          maxit=100000, graph_block=32, stream=None):
+        """x with (Mbar - c K_W) x = Mbar f + c G_b (FP64 CG).  wall_dirichlet: uint8 device
+        tensor [nd] flagging Dirichlet wall edges; wall_values: float64 [nd, p+1] data."""
+        import torch
         x = self._new(self.main_shape) if x is None else x
+        mask_p = _vp(0)
+        if wall_dirichlet is not None:
+            if (wall_dirichlet.dtype != torch.uint8 or not wall_dirichlet.is_cuda or
+                    tuple(wall_dirichlet.shape) != (self.mesh.nd,) or
+                    not wall_dirichlet.is_contiguous()):
+                raise ValueError(f"wall_dirichlet must be a contiguous uint8 cuda tensor [{self.mesh.nd}]")
+            mask_p = _vp(wall_dirichlet.data_ptr())
+        vals_p = _vp(0)
+        if wall_values is not None:
+            vals_p = self._dev(wall_values, (self.mesh.nd, self.p + 1), "wall_values")
         prm = make_params(rtol, maxit, False, graph_block)
         rep = sld_cg_report()
         st = _lib.sld_viscous_solve(self.handle, self._dev(f, self.main_shape, "f"), float(c),
-                                    self._dev(x, self.main_shape, "x"), ctypes.byref(prm),
-                                    ctypes.byref(rep), self._stream(stream))
+                                    mask_p, vals_p, self._dev(x, self.main_shape, "x"),
+                                    ctypes.byref(prm), ctypes.byref(rep), self._stream(stream))
         report = report_dict(rep, st)
         if st not in (0, 5):
             _check(st)

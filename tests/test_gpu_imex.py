@@ -72,7 +72,7 @@ def test_viscous_solve_matches_oracle(torch_dev, p, periodic):
     torch = torch_dev
     _say(f"[imex viscous] p={p} periodic={periodic}")
     od, disc = _pair(6, p, periodic, seed=6)
-    K = solve.assemble_K(od)
+    K = oimex.assemble_K_walls(od, None)  # walls (if any) have zero flux
     f = random_vector((od.mesh.ne, 1, od.nphi), seed=30 + p)
     for c in (0.0, 1e-3, 0.05):
         x, rep = disc.sld_viscous_solve(torch.from_numpy(np.ascontiguousarray(f[:, 0])).to("cuda:0"),
@@ -218,3 +218,40 @@ def test_imex_inviscid_and_mixed_pressure_match_oracle(torch_dev, p):
             assert rv <= 1e-9 and rp <= 1e-9
             if nu == 0.0:
                 assert all(r["iters"] == 0 for r in rep["viscous"])
+
+
+def _edge_nodes_xy(od):
+    """[nd, p+1, 2] positions of the p+1 nodes of every edge, counted from its first vertex."""
+    t = np.arange(od.p + 1) / od.p
+    m = od.mesh
+    return m.A[:, None, :] + t[None, :, None] * (m.B - m.A)[:, None, :]
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_diffusion_walls_match_oracle(torch_dev, p):
+    """Implicit diffusion on the walled unit box (the cavity's walls): zero flux everywhere;
+    Dirichlet everywhere with data; Dirichlet side walls with data and zero-flux top and bottom.
+    GPU solution against the oracle's sparse LU of (Mbar - c K_W) x = Mbar f + c G_b."""
+    torch = torch_dev
+    _say(f"[diffusion walls] p={p}")
+    od, disc = _pair(6, p, periodic=False, seed=8)
+    m = od.mesh
+    wall = ~m.interior
+    mid = 0.5 * (m.A + m.B)
+    side = wall & ((np.abs(mid[:, 0]) < 1e-12) | (np.abs(mid[:, 0] - 1.0) < 1e-12))
+    data = lambda q: 0.5 - q[..., 0] + 0.3 * np.sin(3.0 * q[..., 1])
+    vals = np.ascontiguousarray(data(_edge_nodes_xy(od)))
+    f = random_vector((m.ne, 1, od.nphi), seed=60 + p)
+    ft = torch.from_numpy(np.ascontiguousarray(f[:, 0])).to("cuda:0")
+    for name, mask, with_data in (("flux", None, False), ("dirichlet", wall, True),
+                                  ("sides", side, True)):
+        KW = oimex.assemble_K_walls(od, mask)
+        gb = oimex.dirichlet_rhs(od, mask, data) if with_data else None
+        for c in (1e-3, 0.05):
+            want = oimex.diffusion_solve(od, KW, f, c, gb)[:, 0]
+            mt = None if mask is None else torch.from_numpy(mask.astype(np.uint8)).to("cuda:0")
+            vt = torch.from_numpy(vals).to("cuda:0") if with_data else None
+            x, rep = disc.sld_viscous_solve(ft, c, wall_dirichlet=mt, wall_values=vt, rtol=1e-13)
+            r = _rel(x.cpu().numpy(), want)
+            _say(f"    {name} c={c}: iters {rep['iters']} rel {r:.2e}")
+            assert rep["converged"] and r <= 1e-10
