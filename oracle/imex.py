@@ -279,6 +279,50 @@ def imex_step(disc: OracleDisc, K: sp.csr_matrix, vhat: np.ndarray, dt: float, n
     return vnew, pi, {"vbar": vbar, "vF": vF, "vs_bar": vs_bar, "vs": vs, "b": b}
 
 
+# ---------------------------------------------------------------- Boussinesq cavity
+# R = 0 step of the natural-convection model (eqs. nc.1-nc.3, eq. pressure_IMEX), readings:
+#   * nondimensional form with g beta = Delta T = L = 1: nu = sqrt(Pr / Ra), kappa =
+#     1 / sqrt(Ra Pr); the momentum source (1 - beta dT) g keeps only its buoyancy part
+#     (0, g beta T) -- the constant gravity is a hydrostatic pressure gradient, absorbed into p;
+#   * no-slip walls: the wall dual cells carry zero velocity (prescribed), and the viscous solve
+#     has Dirichlet cells with zero data on every wall;
+#   * temperature: Dirichlet data on the flagged walls (the heated and cooled sides), zero flux
+#     on the others (adiabatic);
+#   * buoyancy enters with the new temperature: v* += dt g beta (0, L_md(T*)) on interior cells,
+#     before the pressure projection (eq. nc.2 with the source of eq. pressure_IMEX).
+
+
+def cavity_operators(disc: OracleDisc, temp_mask, temp_trace):
+    """(K, K_V, K_T, G_T): pressure operator, no-slip viscous operator, temperature diffusion
+    operator and its boundary-data vector."""
+    m = disc.mesh
+    K = solve.assemble_K(disc)
+    KV = assemble_K_walls(disc, ~m.interior)
+    KT = assemble_K_walls(disc, temp_mask)
+    GT = dirichlet_rhs(disc, temp_mask, temp_trace)
+    return K, KV, KT, GT
+
+
+def cavity_step(disc: OracleDisc, ops, vhat: np.ndarray, T: np.ndarray, dt: float, nu: float,
+                kappa: float, gbeta: float):
+    """One R = 0 step.  vhat [nd, 2, Npsi], T [ne, Nphi] -> (vhat, T, pi)."""
+    m = disc.mesh
+    K, KV, KT, GT = ops
+    vbar = dual_to_main(disc, vhat)
+    vF = advect.sl_advect(disc, vbar, vbar, dt)
+    TF = advect.sl_advect(disc, vbar, T[:, None, :], dt)
+    Ts = diffusion_solve(disc, KT, TF, dt * kappa, GT)[:, 0]
+    vsb = diffusion_solve(disc, KV, vF, dt * nu, None)
+    vs = main_to_dual(disc, vsb)
+    tb = main_to_dual(disc, Ts[:, None, :])[:, 0]
+    vs[:, 1] += dt * gbeta * tb
+    vs[~m.interior] = 0.0
+    b = solve.pressure_rhs(disc, vs, 1.0 / dt)
+    pi = pressure_solve(disc, K, b)
+    vnew = solve.velocity_correction(disc, vs, pi, dt)
+    return vnew, Ts, pi
+
+
 # ---------------------------------------------------------------- Taylor-Green vortex
 def tgv_velocity(xy: np.ndarray, t: float, nu: float) -> np.ndarray:
     """Exact Taylor-Green velocity (Section 5, with g = 0): [..., 2]."""

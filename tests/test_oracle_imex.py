@@ -222,3 +222,56 @@ def test_dirichlet_diffusion_keeps_the_linear_steady_state():
     for c in (1e-3, 0.1, 10.0):
         out = imex.diffusion_solve(d, KS, u, c, gb)
         assert np.abs(out - u).max() <= 1e-11
+
+
+def _cavity(n, p, jitter=0.0, seed=4):
+    xy, tri, per = lattice_mesh(n, seed=seed, periodic=False, length=1.0, jitter=jitter)
+    d = OracleDisc(OracleMesh(xy, tri, per), p)
+    _, side = _wall_side_masks(d)
+    ops = imex.cavity_operators(d, side, lambda q: 0.5 - q[..., 0])
+    return d, ops
+
+
+def test_cavity_conduction_state_is_steady():
+    """Without buoyancy the conduction profile T = 0.5 - x at rest is a steady state."""
+    d, ops = _cavity(5, 2, jitter=0.1)
+    m = d.mesh
+    T = 0.5 - d.main_node_xy()[..., 0]
+    v = np.zeros((m.nd, 2, d.npsi))
+    for _ in range(2):
+        v, T2, pi = imex.cavity_step(d, ops, v, T, 0.1, 3e-3, 4e-3, 0.0)
+        assert np.abs(T2 - T).max() <= 1e-11 and np.abs(v).max() <= 1e-12
+        T = T2
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_cavity_first_step_symmetry_and_buoyancy(p):
+    """The differentially heated cavity is symmetric under the point reflection about the box
+    centre with T -> -T, v -> -v, p -> p.  From rest the walk is the identity, every other
+    operator is an exact integral, and the unjittered mesh is symmetric, so the first step is
+    symmetric to rounding; the hot fluid rises at the left wall and sinks at the right; the
+    velocity is divergence-free and zero on the wall cells."""
+    from scipy.spatial import cKDTree
+    d, ops = _cavity(5, p)
+    m = d.mesh
+    v = np.zeros((m.nd, 2, d.npsi))
+    T = np.zeros((m.ne, d.nphi))
+    v, T, pi = imex.cavity_step(d, ops, v, T, 0.1, 2.7e-3, 3.7e-3, 1.0)
+    xyn, cen = d.main_node_xy(), m.centroid
+    _, ti = cKDTree(cen).query(1.0 - cen)
+    for i in range(m.ne):
+        nk = cKDTree(xyn[ti[i]]).query(1.0 - xyn[i])[1]
+        assert np.abs(T[i] + T[ti[i]][nk]).max() <= 1e-13
+        assert np.abs(pi[i] - pi[ti[i]][nk]).max() <= 1e-13 * max(np.abs(pi).max(), 1.0)
+    dn = d.dual_node_xy()
+    mid = 0.5 * (m.A + m.B)
+    _, ej = cKDTree(mid).query(1.0 - mid)
+    for j in np.nonzero(m.interior)[0]:
+        nk = cKDTree(dn[ej[j]]).query(1.0 - dn[j])[1]
+        assert np.abs(v[j] + v[ej[j]][:, nk]).max() <= 1e-13
+    xs = dn[..., 0]
+    inner = m.interior[:, None] & np.isfinite(xs)
+    vy = v[:, 1, :]
+    assert vy[inner & (xs < 0.3)].mean() > 0.0 > vy[inner & (xs > 0.7)].mean()
+    assert np.abs(v[~m.interior]).max() == 0.0
+    assert np.linalg.norm(solve.divergence(d, v)) <= 1e-12 * np.abs(v).max()
