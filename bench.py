@@ -283,6 +283,88 @@ def bench_imex(args, torch, sld, lattice_mesh):
     print(json.dumps(res), flush=True)
 
 
+def bench_cavity(args, torch, sld, lattice_mesh):
+    """One step = one R = 0 Boussinesq step of the differentially heated cavity (Ra = 1e5,
+    Pr = 0.71, side walls at +-0.5, adiabatic top and bottom, no-slip), dt = 0.5 h, from rest;
+    pressure solve in the precision asked for (default mixed, rtol 1e-10), diffusion solves
+    FP64 1e-12."""
+    wl = WORKLOADS[args.workload]
+    n, p = wl["n"], wl["p"]
+    xy, tri, per = lattice_mesh(n, seed=wl["seed"], periodic=False, length=1.0)
+    mesh = sld.Mesh(xy, tri, per, device=0)
+    disc = sld.Disc(mesh, p)
+    ne, nd, nphi = mesh.ne, mesh.nd, disc.nphi
+    left, right, _, _ = mesh.edges()
+    nodes = disc.dual_nodes()  # edge nodes from the first vertex: dual DOFs (p - m, m)
+    enodes = np.stack([nodes[:, m * (p + 1) + (p - m)] for m in range(p + 1)], axis=1)
+    mid = enodes.mean(axis=1)
+    wall = right < 0
+    side = wall & ((np.abs(mid[:, 0]) < 1e-9) | (np.abs(mid[:, 0] - 1.0) < 1e-9))
+    mask = torch.from_numpy(side.astype(np.uint8)).to("cuda:0")
+    vals = torch.from_numpy(np.ascontiguousarray(0.5 - enodes[..., 0])).to("cuda:0")
+    Ra, Pr = 1e5, 0.71
+    nu, kappa = math.sqrt(Pr / Ra), 1.0 / math.sqrt(Ra * Pr)
+    dt = 0.5 / n
+    precision = args.precision if args.precision_given else "mixed"
+    rtol = args.rtol if args.rtol is not None else (1e-12 if precision == "fp64" else 1e-10)
+    v = torch.zeros(disc.dual_shape, dtype=torch.float64, device="cuda:0")
+    T = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    pres = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    state = sld.State(disc)
+    steps = max(args.steps, 1) * 40
+
+    def step():
+        return state.sld_boussinesq_step(v, T, pres, dt, nu, kappa, 1.0, temp_dirichlet=mask,
+                                         temp_values=vals, rtol=rtol, precision=precision,
+                                         graph_block=args.graph_block)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        reps.append(step())
+        if (k + 1) % 50 == 0:
+            print(f"cavity step {k + 1}/{steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    p_iters = sum(r["pressure"]["iters"] for r in reps)
+    p_sec = sum(r["pressure"]["seconds"] for r in reps)
+    word = 8 if precision == "fp64" else 4
+    step_us = 1e6 * p_sec / max(p_iters, 1)
+    sbytes = step_bytes_per_tri(nphi, word) * ne
+    achieved = sbytes / (step_us * 1e-6) / 1e9
+    res = {
+        "metric": "Boussinesq cavity (R = 0) steps/s",
+        "value": steps / elapsed, "unit": "steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: differentially heated cavity, Ra = 1e5, "
+                               f"Pr = 0.71, walled jittered {n}x{n}x2 = {ne} triangles, p={p}, "
+                               f"dt = 0.5 h, {steps} steps from rest, pressure {precision} "
+                               f"rtol {rtol:g}",
+                   "triangles": ne, "p": p, "dt": dt, "Ra": Ra, "Pr": Pr},
+        "pressure_cg_iters_per_step": p_iters / steps,
+        "pressure_ms_per_step": 1e3 * p_sec / steps,
+        "temperature_cg_iters_per_step": sum(r["temperature"]["iters"] for r in reps) / steps,
+        "viscous_cg_iters_per_step": sum(r["viscous"][0]["iters"] + r["viscous"][1]["iters"]
+                                         for r in reps) / steps,
+        "max_pressure_rel_res_true": max(r["pressure"]["rel_res_true"] for r in reps),
+        "max_velocity": float(v.abs().max()), "temperature_range": [float(T.min()), float(T.max())],
+        "divergence_norm_at_end": float(torch.linalg.norm(disc.sld_divergence(v))),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_cg_step<{p}, {'double' if word == 8 else 'float'}> (pressure CG iteration)",
+                     "kernel_us_source": "pressure solve wall time / iterations",
+                     "kernel_us": step_us, "bytes_per_launch": sbytes},
+        "cpu_baseline": None,
+        "cpu_baseline_note": "the oracle's step on this mesh (pure-Python walks, sparse LU of "
+                             "the 786k-DOF diffusion systems) is not runnable in minutes",
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,12 +379,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sl-advect", action="store_true",
                     help="measure the semi-Lagrangian advection kernel instead (3 fields, CFL 0.5)")
+    ap.add_argument("--cavity", action="store_true",
+                    help="measure R = 0 Boussinesq cavity steps instead (40 x --steps steps; "
+                         "workload cavity256_p2 by default, mixed pressure)")
     ap.add_argument("--imex", action="store_true",
                     help="measure R = 0 SL-IMEX Taylor-Green steps instead (10 x --steps steps)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy MIB MiB device-to-device three times "
                          "(reference kernel for HBM byte counters)")
     args = ap.parse_args()
+    args.precision_given = any(a.startswith("--precision") for a in sys.argv[1:])
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}); the "
               "multi-GPU sharding of the pressure solve is a design note, not a measured path",
@@ -315,6 +401,13 @@ def main():
 
     if args.sl_advect:
         bench_sl_advect(args, torch, sld, lattice_mesh, random_fourier_field)
+        return
+    if args.cavity:
+        if not any(a.startswith("--workload") for a in sys.argv[1:]):
+            args.workload = "cavity256_p2"
+        if not WORKLOADS[args.workload].get("walls"):
+            sys.exit("--cavity runs the walled workloads")
+        bench_cavity(args, torch, sld, lattice_mesh)
         return
     if args.imex:
         if WORKLOADS[args.workload].get("walls"):

@@ -281,6 +281,41 @@ typedef struct {
 sld_status sld_imex_step(sld_state state, const sld_imex_params* params, double dt, double* v,
                          double* p, sld_imex_report* report, void* stream);
 
+/* One R = 0 step of the Boussinesq natural-convection model (eqs. nc.1-nc.3 with the sources
+ * of eq. pressure_IMEX) in a closed box, nondimensional with g beta = Delta T = L = 1 (so
+ * nu = sqrt(Pr/Ra), kappa = 1/sqrt(Ra Pr) for the differentially heated cavity):
+ *   1. vbar = L_dm(v); v and T advected to the feet of vbar over dt (sld_sl_advect)
+ *   2. T: (Mbar - dt kappa K_W) T = Mbar T_F + dt kappa G_b with Dirichlet data temp_values
+ *      on the walls flagged in temp_dirichlet and zero flux on the others (sld_viscous_solve)
+ *   3. vbar*: (Mbar - dt nu K_W) vbar* = Mbar vbar_F per component, no-slip: Dirichlet zero on
+ *      every wall
+ *   4. v* = L_md(vbar*) + dt g beta (0, L_md(T)) on interior cells, zero on the wall cells
+ *      (prescribed no-slip velocity; the constant gravity is absorbed into the pressure)
+ *   5. K p = (1/dt) D v*, int p = 0; v = v* - dt Mhat^{-1} Q p
+ * temp_dirichlet device uint8 [nd] (NULL: all walls adiabatic), temp_values device float64
+ * [nd][p+1] at the edges' nodes from their first vertex (NULL: zero data).
+ * v device [nd][2][N_psi], T device [ne][N_phi]: in at t, out at t + dt.  p device
+ * [ne][N_phi] out (in: initial guess if params->pressure.warm_start).  No aliasing.
+ * SLD_E_INVALID for bad arguments, R != 0 or a mesh without walls.  Blocks until done. */
+typedef struct {
+    double nu, kappa, gbeta;  /* viscosity, thermal diffusivity, g beta (>= 0, >= 0, any) */
+    int32_t R;                /* 0 only */
+    sld_cg_params pressure;   /* the pressure solve (FP64 or mixed) */
+    sld_cg_params viscous;    /* the diffusion solves (FP64) */
+} sld_boussinesq_params;
+
+typedef struct {
+    sld_cg_report pressure;
+    sld_cg_report viscous[2];
+    sld_cg_report temperature;
+    double seconds;
+} sld_boussinesq_report;
+
+sld_status sld_boussinesq_step(sld_state state, const sld_boussinesq_params* params, double dt,
+                               const uint8_t* temp_dirichlet, const double* temp_values,
+                               double* v, double* T, double* p, sld_boussinesq_report* report,
+                               void* stream);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching of independent pressure solves (the paper's pressure stage of
  * eq. pressure_final, one per request) and IMEX steps (sld_server_submit_imex).  Requests are queued as they arrive; a worker thread

@@ -1084,6 +1084,10 @@ void free_state(sld_state_s* st) {
     dfree(st->vsbar);
     dfree(st->vs);
     dfree(st->b);
+    dfree(st->wall_all);
+    dfree(st->tfoot);
+    dfree(st->gbt);
+    dfree(st->tdual);
     delete st;
 }
 
@@ -1177,6 +1181,25 @@ sld_status sld_state_create(sld_disc d, sld_state* out) {
     if (e == hipSuccess) e = dalloc(&st->vsbar, 2 * nm);
     if (e == hipSuccess) e = dalloc(&st->vs, ndv);
     if (e == hipSuccess) e = dalloc(&st->b, nm);
+    const sld_mesh_s* m = d->mesh;
+    std::vector<unsigned char> wall_h;
+    for (int64_t j = 0; j < m->nd; ++j)
+        if (m->right[j] < 0) {
+            wall_h.assign(size_t(m->nd), 0);
+            break;
+        }
+    if (!wall_h.empty()) {
+        for (int64_t j = 0; j < m->nd; ++j) wall_h[j] = m->right[j] < 0 ? 1 : 0;
+        if (e == hipSuccess) e = dalloc(&st->wall_all, size_t(m->nd));
+        if (e == hipSuccess) e = dalloc(&st->tfoot, nm);
+        if (e == hipSuccess) e = dalloc(&st->gbt, nm);
+        if (e == hipSuccess) e = dalloc(&st->tdual, size_t(m->nd) * d->npsi);
+        if (e == hipSuccess) {
+            Uploader up;
+            up.copy(st->wall_all, wall_h.data(), wall_h.size());
+            e = up.finish();
+        }
+    }
     if (e != hipSuccess) {
         free_state(st);
         sld_set_error(std::string("sld_state_create: device allocation failed: ") + hipGetErrorString(e));
@@ -1236,6 +1259,83 @@ sld_status sld_imex_step(sld_state st, const sld_imex_params* prm, double dt, do
     sld_status e = cg_solve_impl(d, st->b, p, &prm->pressure, &r->pressure, s, 0.0);
     if (e != SLD_OK) return done(e);
     SLD_HIP_CHECK(launch_gradient(d, p, st->vs, -a_ss * dt, v, s));
+    SLD_HIP_CHECK(hipStreamSynchronize(s));
+    return done(SLD_OK);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+sld_status sld_boussinesq_step(sld_state st, const sld_boussinesq_params* prm, double dt,
+                               const uint8_t* temp_dirichlet, const double* temp_values,
+                               double* v, double* T, double* p, sld_boussinesq_report* rep,
+                               void* stream) {
+    SLD_REQUIRE(st && prm && v && T && p, SLD_E_INVALID, "sld_boussinesq_step: NULL argument");
+    SLD_REQUIRE(v != p && v != T && T != p, SLD_E_INVALID,
+                "sld_boussinesq_step: v, T and p must not alias");
+    SLD_REQUIRE(std::isfinite(dt) && dt > 0.0, SLD_E_INVALID, "sld_boussinesq_step: dt must be > 0");
+    SLD_REQUIRE(std::isfinite(prm->nu) && prm->nu >= 0.0 && std::isfinite(prm->kappa) &&
+                    prm->kappa >= 0.0 && std::isfinite(prm->gbeta),
+                SLD_E_INVALID, "sld_boussinesq_step: nu, kappa must be finite and >= 0, gbeta finite");
+    SLD_REQUIRE(prm->R == 0, SLD_E_INVALID, "sld_boussinesq_step: only R = 0 is built");
+    SLD_REQUIRE(prm->viscous.precision == 0, SLD_E_INVALID,
+                "sld_boussinesq_step: the diffusion solves run in FP64 (precision 0)");
+    sld_disc d = st->disc;
+    SLD_REQUIRE(st->wall_all != nullptr, SLD_E_INVALID,
+                "sld_boussinesq_step: the mesh has no walls (a closed cavity is needed)");
+    DeviceGuard dg(d->mesh->device);
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    sld_boussinesq_report local{};
+    sld_boussinesq_report* r = rep ? rep : &local;
+    *r = sld_boussinesq_report{};
+    const int64_t ne = d->mesh->ne;
+    const int N = d->nphi;
+    auto done = [&](sld_status e) {
+        r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return e;
+    };
+    // transport: velocity and temperature at the feet of the velocity on the main grid
+    SLD_HIP_CHECK(launch_dual_to_main(d, v, 2, st->vbar, 2 * N, N, s));
+    SLD_HIP_CHECK(launch_sl_advect(d, st->vbar, st->vbar, 2, dt, st->vfoot, s));
+    SLD_HIP_CHECK(launch_sl_advect(d, st->vbar, T, 1, dt, st->tfoot, s));
+    // temperature: implicit diffusion with Dirichlet data on the flagged walls
+    const double ct = dt * prm->kappa;
+    if (ct > 0.0) {
+        const double* gb = nullptr;
+        if (temp_dirichlet && temp_values) {
+            SLD_HIP_CHECK(launch_dirichlet_rhs(d, temp_dirichlet, temp_values, st->gbt, s));
+            gb = st->gbt;
+        }
+        sld_status e = viscous_field(d, st->tfoot, N, 0, 0, ct, temp_dirichlet, gb, T, st->b,
+                                     &prm->viscous, &r->temperature, s);
+        if (e != SLD_OK) return done(e);
+    } else {
+        SLD_HIP_CHECK(hipMemcpyAsync(T, st->tfoot, sizeof(double) * ne * N,
+                                     hipMemcpyDeviceToDevice, s));
+    }
+    // velocity: implicit viscosity with no-slip walls
+    const double cv = dt * prm->nu;
+    if (cv > 0.0) {
+        for (int comp = 0; comp < 2; ++comp) {
+            sld_status e = viscous_field(d, st->vfoot, 2 * N, N, comp, cv, st->wall_all, nullptr,
+                                         st->vsbar + comp * ne * N, st->b, &prm->viscous,
+                                         &r->viscous[comp], s);
+            if (e != SLD_OK) return done(e);
+        }
+        SLD_HIP_CHECK(launch_main_to_dual(d, st->vsbar, 2, N, ne * N, st->vs, s));
+    } else {
+        SLD_HIP_CHECK(launch_main_to_dual(d, st->vfoot, 2, 2 * N, N, st->vs, s));
+    }
+    // buoyancy with the new temperature, zero velocity on the wall cells
+    SLD_HIP_CHECK(launch_main_to_dual(d, T, 1, N, 0, st->tdual, s));
+    SLD_HIP_CHECK(launch_buoyancy(d, st->tdual, dt * prm->gbeta, st->vs, s));
+    // pressure projection
+    SLD_HIP_CHECK(launch_divergence(d, st->vs, 1.0 / dt, st->b, s));
+    sld_status e = cg_solve_impl(d, st->b, p, &prm->pressure, &r->pressure, s, 0.0);
+    if (e != SLD_OK) return done(e);
+    SLD_HIP_CHECK(launch_gradient(d, p, st->vs, -dt, v, s));
     SLD_HIP_CHECK(hipStreamSynchronize(s));
     return done(SLD_OK);
 }

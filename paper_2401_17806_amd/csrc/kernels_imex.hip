@@ -256,6 +256,25 @@ __global__ __launch_bounds__(kBlockX) void k_dirichlet_rhs(const RefOps<P>* __re
     for (int k = 0; k < N; ++k) out[i * N + k] = y[k];
 }
 
+// Boussinesq: v*[j][1][:] += coef * t[j][:] on interior dual cells (buoyancy (0, g beta T) of
+// eqs. nc.2 / pressure_IMEX over the step), and no-slip: zero velocity on the wall cells.
+template <int P>
+__global__ __launch_bounds__(kBlockX) void k_buoyancy(const int4* __restrict__ edges, int64_t nd,
+                                                     const double* __restrict__ t, double coef,
+                                                     double* __restrict__ vs) {
+    constexpr int NPSI = (P + 1) * (P + 1);
+    const int64_t j = (int64_t)blockIdx.x * kBlockX + threadIdx.x;
+    if (j >= nd) return;
+    double* o = vs + j * 2 * NPSI;
+    if (edges[j].y < 0) {
+#pragma unroll
+        for (int k = 0; k < 2 * NPSI; ++k) o[k] = 0.0;
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < NPSI; ++k) o[NPSI + k] = fma(coef, t[j * NPSI + k], o[NPSI + k]);
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlockX - 1) / kBlockX); }
 
 template <int P>
@@ -306,5 +325,13 @@ hipError_t launch_dirichlet_rhs(const sld_disc_s* d, const unsigned char* edge_m
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_dirichlet_rhs<PP>, dim3(nblk(m->ne)), dim3(kBlockX), 0,
                                           s, ops_of<PP>(d), m->geo, m->nbr, m->tedges, m->ne,
                                           edge_mask, values, out));
+    return hipGetLastError();
+}
+
+hipError_t launch_buoyancy(const sld_disc_s* d, const double* t, double coef, double* vs,
+                           hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_buoyancy<PP>, dim3(nblk(m->nd)), dim3(kBlockX), 0, s,
+                                          m->edges, m->nd, t, coef, vs));
     return hipGetLastError();
 }

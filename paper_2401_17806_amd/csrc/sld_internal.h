@@ -150,3 +150,6 @@ hipError_t launch_mass_rhs(const sld_disc_s* d, const double* f, int64_t f_is, i
 // G_b [ne][N] of Dirichlet data on the flagged wall edges (mask and values [nd][p+1] device)
 hipError_t launch_dirichlet_rhs(const sld_disc_s* d, const unsigned char* edge_mask,
                                 const double* values, double* out, hipStream_t s);
+// v*[j][1] += coef t[j] on interior dual cells, v*[j] = 0 on wall cells (t [nd][Npsi])
+hipError_t launch_buoyancy(const sld_disc_s* d, const double* t, double coef, double* vs,
+                           hipStream_t s);

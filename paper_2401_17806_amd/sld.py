@@ -56,6 +56,16 @@ class sld_imex_report(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class sld_boussinesq_params(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("kappa", ctypes.c_double), ("gbeta", ctypes.c_double),
+                ("R", _i32), ("pressure", sld_cg_params), ("viscous", sld_cg_params)]
+
+
+class sld_boussinesq_report(ctypes.Structure):
+    _fields_ = [("pressure", sld_cg_report), ("viscous", sld_cg_report * 2),
+                ("temperature", sld_cg_report), ("seconds", ctypes.c_double)]
+
+
 def _sig(name, args, res=ctypes.c_int):
     f = getattr(_lib, name)
     f.argtypes = args
@@ -94,6 +104,8 @@ _sig("sld_state_create", [_vp, ctypes.POINTER(_vp)])
 _sig("sld_state_destroy", [_vp], None)
 _sig("sld_imex_step", [_vp, ctypes.POINTER(sld_imex_params), ctypes.c_double, _vp, _vp,
                        ctypes.POINTER(sld_imex_report), _vp])
+_sig("sld_boussinesq_step", [_vp, ctypes.POINTER(sld_boussinesq_params), ctypes.c_double, _vp,
+                             _vp, _vp, _vp, _vp, ctypes.POINTER(sld_boussinesq_report), _vp])
 _sig("sld_server_create", [_i32, ctypes.c_uint64, _i32, ctypes.POINTER(_vp)])
 _sig("sld_server_submit", [_vp, _vp, _vp, _vp, ctypes.POINTER(sld_cg_params), _vp,
                            ctypes.POINTER(ctypes.c_uint64)])
@@ -112,6 +124,7 @@ EXPORTED = [
     "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_disc_footprint",
     "sld_sl_advect", "sld_ref_operator", "sld_dual_to_main", "sld_main_to_dual",
     "sld_viscous_solve", "sld_state_create", "sld_state_destroy", "sld_imex_step",
+    "sld_boussinesq_step",
     "sld_server_create", "sld_server_submit", "sld_server_submit_imex", "sld_server_poll",
     "sld_server_stats",
     "sld_server_destroy",
@@ -448,6 +461,39 @@ class State:
                                 ctypes.byref(rep), d._stream(stream))
         out = {"pressure": report_dict(rep.pressure, st),
                "viscous": [report_dict(rep.viscous[k], st) for k in range(2)],
+               "seconds": rep.seconds, "status": STATUS.get(st, st)}
+        if st not in (0, 5):
+            _check(st)
+        return out
+
+    def sld_boussinesq_step(self, v, T, p, dt, nu, kappa, gbeta, temp_dirichlet=None,
+                            temp_values=None, R=0, rtol=1e-12, visc_rtol=1e-12, maxit=200000,
+                            graph_block=32, warm_start=True, precision="fp64", stream=None):
+        """One Boussinesq step in place: v [nd, 2, N_psi], T [ne, N_phi]; p [ne, N_phi] out.
+        temp_dirichlet: uint8 cuda tensor [nd]; temp_values: float64 [nd, p+1]."""
+        import torch
+        d = self.disc
+        mask_p = _vp(0)
+        if temp_dirichlet is not None:
+            if (temp_dirichlet.dtype != torch.uint8 or not temp_dirichlet.is_cuda or
+                    tuple(temp_dirichlet.shape) != (d.mesh.nd,) or
+                    not temp_dirichlet.is_contiguous()):
+                raise ValueError(f"temp_dirichlet must be a contiguous uint8 cuda tensor [{d.mesh.nd}]")
+            mask_p = _vp(temp_dirichlet.data_ptr())
+        vals_p = _vp(0) if temp_values is None else d._dev(temp_values, (d.mesh.nd, d.p + 1),
+                                                           "temp_values")
+        prm = sld_boussinesq_params(float(nu), float(kappa), float(gbeta), int(R),
+                                    make_params(rtol, maxit, warm_start, graph_block, False,
+                                                precision),
+                                    make_params(visc_rtol, maxit, True, graph_block))
+        rep = sld_boussinesq_report()
+        st = _lib.sld_boussinesq_step(self.handle, ctypes.byref(prm), float(dt), mask_p, vals_p,
+                                      d._dev(v, d.dual_shape, "v"), d._dev(T, d.main_shape, "T"),
+                                      d._dev(p, d.main_shape, "p"), ctypes.byref(rep),
+                                      d._stream(stream))
+        out = {"pressure": report_dict(rep.pressure, st),
+               "viscous": [report_dict(rep.viscous[k], st) for k in range(2)],
+               "temperature": report_dict(rep.temperature, st),
                "seconds": rep.seconds, "status": STATUS.get(st, st)}
         if st not in (0, 5):
             _check(st)

@@ -255,3 +255,67 @@ def test_diffusion_walls_match_oracle(torch_dev, p):
             r = _rel(x.cpu().numpy(), want)
             _say(f"    {name} c={c}: iters {rep['iters']} rel {r:.2e}")
             assert rep["converged"] and r <= 1e-10
+
+
+def _cavity_pair(n, p, seed=12, jitter=0.1):
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(n, seed=seed, periodic=False, length=1.0, jitter=jitter)
+    od = OracleDisc(OracleMesh(xy, tri, per), p)
+    return od, sld.Disc(sld.Mesh(xy, tri, per, device=0), p)
+
+
+def _side_mask(od):
+    m = od.mesh
+    mid = 0.5 * (m.A + m.B)
+    return (~m.interior) & ((np.abs(mid[:, 0]) < 1e-12) | (np.abs(mid[:, 0] - 1.0) < 1e-12))
+
+
+@pytest.mark.parametrize("p,precision", [(1, "fp64"), (2, "fp64"), (3, "fp64"), (2, "mixed")])
+def test_boussinesq_steps_match_oracle(torch_dev, p, precision):
+    """Differentially heated cavity (Ra = 1e5, Pr = 0.71, side walls at +-0.5, adiabatic top and
+    bottom, no-slip): four R = 0 steps from rest on a jittered 6x6x2 mesh, velocity, temperature
+    and pressure against the oracle's steps."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    _say(f"[boussinesq] p={p} {precision}")
+    od, disc = _cavity_pair(6, p)
+    m = od.mesh
+    side = _side_mask(od)
+    data = lambda q: 0.5 - q[..., 0]
+    ops = oimex.cavity_operators(od, side, data)
+    Ra, Pr = 1e5, 0.71
+    nu, kappa = math.sqrt(Pr / Ra), 1.0 / math.sqrt(Ra * Pr)
+    dt = 0.5 / 6
+    v = np.zeros((m.nd, 2, od.npsi))
+    T = np.zeros((m.ne, od.nphi))
+    vg = torch.zeros(disc.dual_shape, dtype=torch.float64, device="cuda:0")
+    Tg = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    pg = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    mask = torch.from_numpy(side.astype(np.uint8)).to("cuda:0")
+    vals = torch.from_numpy(np.ascontiguousarray(data(_edge_nodes_xy(od)))).to("cuda:0")
+    st = sld.State(disc)
+    rtol = 1e-13 if precision == "fp64" else 1e-11
+    for k in range(4):
+        v, T, pi = oimex.cavity_step(od, ops, v, T, dt, nu, kappa, 1.0)
+        rep = st.sld_boussinesq_step(vg, Tg, pg, dt, nu, kappa, 1.0, temp_dirichlet=mask,
+                                     temp_values=vals, rtol=rtol, visc_rtol=1e-13,
+                                     precision=precision)
+        rv, rt, rp = (_rel(vg.cpu().numpy(), v), _rel(Tg.cpu().numpy(), T),
+                      _rel(pg.cpu().numpy(), pi))
+        _say(f"    step {k}: v {rv:.2e} T {rt:.2e} p {rp:.2e} status {rep['status']} "
+             f"iters p {rep['pressure']['iters']} T {rep['temperature']['iters']} "
+             f"v {[r['iters'] for r in rep['viscous']]}")
+        assert rep["status"] == "SLD_OK"
+        assert rv <= 1e-9 and rt <= 1e-9 and rp <= 1e-9
+
+
+def test_boussinesq_step_rejects_periodic_mesh(torch_dev):
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    od, disc = _pair(4, 2, seed=9)
+    st = sld.State(disc)
+    v = torch.zeros(disc.dual_shape, dtype=torch.float64, device="cuda:0")
+    T = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    p = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(sld.SldError, match="walls"):
+        st.sld_boussinesq_step(v, T, p, 0.1, 1e-3, 1e-3, 1.0)
