@@ -185,6 +185,39 @@ def assemble_K_walls(disc: OracleDisc, dirichlet_mask=None) -> sp.csr_matrix:
     return (K + Kw).tocsr()
 
 
+def walls_rows(disc: OracleDisc, u: np.ndarray, tri_ids, dirichlet_mask=None) -> np.ndarray:
+    """(K_W u)_i for the triangles in tri_ids only (rows of assemble_K_walls without assembling
+    it), for checks on large meshes: the interior-edge rows of eq. pressure_final plus the wall
+    cells of those triangles."""
+    m = disc.mesh
+    nphi = disc.nphi
+    tri_ids = np.asarray(tri_ids, dtype=np.int64)
+    out = solve.schur_rows(disc, u, tri_ids)
+    J = np.unique(m.tri_edges[tri_ids].ravel())
+    J = J[~m.interior[J]]
+    if J.size == 0:
+        return out
+    dmask = np.zeros(m.nd, dtype=bool) if dirichlet_mask is None else np.asarray(dirichlet_mask, bool)
+    B = np.zeros((J.size, nphi, nphi))
+    isd = dmask[J]
+    if (~isd).any():
+        B[~isd] = _wall_stiffness(disc, J[~isd])
+    if isd.any():
+        h = _left_half(disc.p)
+        blk = disc.edge_blocks(J[isd])
+        Mh = blk["Mhat"][:, h][:, :, h]
+        Ql = blk["Ql"][:, h]
+        Dl = blk["Dl"][:, :, h]
+        E, nh = Mh.shape[0], Mh.shape[1]
+        X = np.linalg.solve(Mh, Ql.reshape(E, nh, nphi * 2)).reshape(E, nh, nphi, 2)
+        B[isd] = np.einsum("ekmc,emlc->ekl", Dl, X)
+    pos = {int(i): t for t, i in enumerate(tri_ids)}
+    for e, j in enumerate(J):
+        i = int(m.left[j])
+        out[pos[i]] += B[e] @ u[i]
+    return out
+
+
 def dirichlet_rhs(disc: OracleDisc, dirichlet_mask, trace) -> np.ndarray:
     """G_b [ne, Nphi] for the data trace(xy [..., 2]) -> [...] on the masked wall edges (taken
     through its values at the edge nodes)."""

@@ -163,3 +163,82 @@ def test_fullsize_cavity_solve_properties(torch_dev):
     assert rel <= 1e-7
     w = od.main_weights()
     assert abs((w * ph).sum()) <= 1e-12 * np.abs(ph).max() * w.sum()
+
+
+def _cavity_setup(torch):
+    from oracle import imex as oimex
+    from paper_2401_17806_amd import sld
+    n, p = 256, 2
+    xy, tri, per = lattice_mesh(n, seed=4, periodic=False, length=1.0)
+    od = OracleDisc(OracleMesh(xy, tri, per), p)
+    disc = sld.Disc(sld.Mesh(xy, tri, per, device=0), p)
+    m = od.mesh
+    mid = 0.5 * (m.A + m.B)
+    side = (~m.interior) & ((np.abs(mid[:, 0]) < 1e-12) | (np.abs(mid[:, 0] - 1.0) < 1e-12))
+    t = np.arange(p + 1) / p
+    enodes = m.A[:, None, :] + t[None, :, None] * (m.B - m.A)[:, None, :]
+    vals = np.ascontiguousarray(0.5 - enodes[..., 0])
+    return oimex, od, disc, side, vals
+
+
+def test_fullsize_cavity_diffusion_residual_on_sampled_rows(torch_dev):
+    """256x256x2 walled unit box, p = 2: the temperature diffusion solve (Dirichlet side walls
+    with data, adiabatic top and bottom) satisfies (Mbar - c K_W) x = Mbar f + c G_b on sampled
+    rows, wall triangles included, computed by the oracle row by row."""
+    torch = torch_dev
+    _say("[fullsize cavity diffusion]")
+    oimex, od, disc, side, vals = _cavity_setup(torch)
+    m = od.mesh
+    f = random_vector((m.ne, od.nphi), seed=91)
+    c = 0.5 / 256 / math.sqrt(1e5 * 0.71)
+    x, rep = disc.sld_viscous_solve(torch.from_numpy(f).to("cuda:0"), c,
+                                    wall_dirichlet=torch.from_numpy(side.astype(np.uint8)).to("cuda:0"),
+                                    wall_values=torch.from_numpy(vals).to("cuda:0"), rtol=1e-12)
+    _say("   report", rep)
+    xh = x.cpu().numpy()
+    ids = np.unique(np.concatenate([np.nonzero(np.isin(np.arange(m.ne), m.left[side]))[0][::7],
+                                    np.random.default_rng(3).choice(m.ne, 256, replace=False)]))
+    Mb = od.main_mass()[ids]
+    gb_all = oimex.dirichlet_rhs(od, side, lambda q: 0.5 - q[..., 0])
+    lhs = np.einsum("ekl,el->ek", Mb, xh[ids]) - c * oimex.walls_rows(od, xh, ids, side)
+    rhs = np.einsum("ekl,el->ek", Mb, f[ids]) + c * gb_all[ids]
+    rel = np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs)
+    _say(f"    sampled residual {rel:.2e} over {ids.size} rows")
+    assert rep["converged"] and rel <= 1e-10
+
+
+def test_fullsize_cavity_steps_properties(torch_dev):
+    """256x256x2 walled unit box, p = 2, Ra = 1e5, Pr = 0.71, twenty R = 0 steps from rest with
+    the mixed-precision pressure solve: divergence-free, zero velocity on the wall cells, the
+    temperature within the wall values up to a small overshoot, and the hot side rising."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    _say("[fullsize cavity steps]")
+    oimex, od, disc, side, vals = _cavity_setup(torch)
+    m = od.mesh
+    nu, kappa = math.sqrt(0.71 / 1e5), 1.0 / math.sqrt(1e5 * 0.71)
+    v = torch.zeros(disc.dual_shape, dtype=torch.float64, device="cuda:0")
+    T = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    p = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    st = sld.State(disc)
+    mask = torch.from_numpy(side.astype(np.uint8)).to("cuda:0")
+    vt = torch.from_numpy(vals).to("cuda:0")
+    for k in range(20):
+        rep = st.sld_boussinesq_step(v, T, p, 0.5 / 256, nu, kappa, 1.0, temp_dirichlet=mask,
+                                     temp_values=vt, rtol=1e-10, precision="mixed",
+                                     graph_block=64)
+        assert rep["status"] == "SLD_OK"
+        dv = float(torch.linalg.norm(disc.sld_divergence(v)))
+        assert dv <= 1e-9 * max(float(v.abs().max()), 1e-300) * math.sqrt(m.ne)
+        if k % 5 == 4:
+            _say(f"    step {k}: |Dv| {dv:.2e} max|v| {float(v.abs().max()):.3e} "
+                 f"T [{float(T.min()):.5f}, {float(T.max()):.5f}] p iters {rep['pressure']['iters']} "
+                 f"{rep['seconds'] * 1e3:.0f} ms")
+    vh = v.cpu().numpy()
+    assert np.abs(vh[~m.interior]).max() == 0.0
+    assert -0.52 <= float(T.min()) and float(T.max()) <= 0.52
+    dn = od.dual_node_xy()
+    xs = dn[..., 0]
+    inner = m.interior[:, None] & np.isfinite(xs)
+    vy = vh[:, 1, :]
+    assert vy[inner & (xs < 0.05)].mean() > 0.0 > vy[inner & (xs > 0.95)].mean()

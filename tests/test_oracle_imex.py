@@ -275,3 +275,14 @@ def test_cavity_first_step_symmetry_and_buoyancy(p):
     assert vy[inner & (xs < 0.3)].mean() > 0.0 > vy[inner & (xs > 0.7)].mean()
     assert np.abs(v[~m.interior]).max() == 0.0
     assert np.linalg.norm(solve.divergence(d, v)) <= 1e-12 * np.abs(v).max()
+
+
+def test_walls_rows_equal_assembled_rows():
+    """walls_rows (sampled rows, used at full size) equals the assembled K_W on every row."""
+    d = _disc(5, 2, periodic=False, seed=15)
+    _, side = _wall_side_masks(d)
+    u = random_vector((d.mesh.ne, d.nphi), seed=77)
+    want = (imex.assemble_K_walls(d, side) @ u.reshape(-1)).reshape(u.shape)
+    ids = np.arange(d.mesh.ne)
+    got = imex.walls_rows(d, u, ids, side)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
