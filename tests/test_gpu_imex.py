@@ -319,3 +319,72 @@ def test_boussinesq_step_rejects_periodic_mesh(torch_dev):
     p = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
     with pytest.raises(sld.SldError, match="walls"):
         st.sld_boussinesq_step(v, T, p, 0.1, 1e-3, 1e-3, 1.0)
+
+
+def _shuffled(n, seed, periodic, length):
+    xy, tri, per = lattice_mesh(n, seed=seed, periodic=periodic, length=length)
+    rng = np.random.default_rng(seed + 1)
+    order = rng.permutation(tri.shape[0])
+    rot = rng.integers(0, 3, size=tri.shape[0])
+    tri2 = np.stack([np.roll(t, -r) for t, r in zip(tri[order], rot)]).astype(np.int32)
+    vperm = rng.permutation(xy.shape[0])
+    inv = np.empty_like(vperm)
+    inv[vperm] = np.arange(vperm.size)
+    return xy[vperm], inv[tri2].astype(np.int32), per
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_imex_and_cavity_on_shuffled_numbering(torch_dev, p):
+    """Random triangle order, rotated local vertices and renumbered vertices: the transfers and
+    two Taylor-Green steps (periodic), and two cavity steps (walled), against the oracle on the
+    same numbering."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    _say(f"[shuffled imex/cavity] p={p}")
+    xy, tri, per = _shuffled(7, 41, True, 2 * np.pi)
+    od = OracleDisc(OracleMesh(xy, tri, per), p)
+    disc = sld.Disc(sld.Mesh(xy, tri, per, device=0), p)
+    m = od.mesh
+    vm = random_vector((m.ne, 2, od.nphi), seed=5)
+    assert _rel(disc.sld_main_to_dual(torch.from_numpy(vm).to("cuda:0")).cpu().numpy(),
+                oimex.main_to_dual(od, vm)) <= 1e-12
+    vd = random_vector((m.nd, 2, od.npsi), seed=6)
+    assert _rel(disc.sld_dual_to_main(torch.from_numpy(vd).to("cuda:0")).cpu().numpy(),
+                oimex.dual_to_main(od, vd)) <= 1e-12
+    K = solve.assemble_K(od)
+    nu, dt = 1e-2, 0.5 * 2 * np.pi / 7
+    v = _tgv0(od, nu)
+    vg = torch.from_numpy(v.copy()).to("cuda:0")
+    pg = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    st = sld.State(disc)
+    for k in range(2):
+        v, pi, _ = oimex.imex_step(od, K, v, dt, nu)
+        st.sld_imex_step(vg, pg, dt, nu, rtol=1e-13, visc_rtol=1e-13)
+        rv, rp = _rel(vg.cpu().numpy(), v), _rel(pg.cpu().numpy(), pi)
+        _say(f"    tgv step {k}: v {rv:.2e} p {rp:.2e}")
+        assert rv <= 1e-9 and rp <= 1e-9
+    # walled: the cavity
+    xy, tri, per = _shuffled(6, 43, False, 1.0)
+    od = OracleDisc(OracleMesh(xy, tri, per), p)
+    disc = sld.Disc(sld.Mesh(xy, tri, per, device=0), p)
+    m = od.mesh
+    side = _side_mask(od)
+    data = lambda q: 0.5 - q[..., 0]
+    ops = oimex.cavity_operators(od, side, data)
+    nu, kappa, dt = math.sqrt(0.71 / 1e5), 1.0 / math.sqrt(1e5 * 0.71), 0.5 / 6
+    v = np.zeros((m.nd, 2, od.npsi))
+    T = np.zeros((m.ne, od.nphi))
+    vg = torch.zeros(disc.dual_shape, dtype=torch.float64, device="cuda:0")
+    Tg = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    pg = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+    st = sld.State(disc)
+    mask = torch.from_numpy(side.astype(np.uint8)).to("cuda:0")
+    vals = torch.from_numpy(np.ascontiguousarray(data(_edge_nodes_xy(od)))).to("cuda:0")
+    for k in range(2):
+        v, T, pi = oimex.cavity_step(od, ops, v, T, dt, nu, kappa, 1.0)
+        st.sld_boussinesq_step(vg, Tg, pg, dt, nu, kappa, 1.0, temp_dirichlet=mask,
+                               temp_values=vals, rtol=1e-13, visc_rtol=1e-13)
+        rv, rt, rp = (_rel(vg.cpu().numpy(), v), _rel(Tg.cpu().numpy(), T),
+                      _rel(pg.cpu().numpy(), pi))
+        _say(f"    cavity step {k}: v {rv:.2e} T {rt:.2e} p {rp:.2e}")
+        assert rv <= 1e-9 and rt <= 1e-9 and rp <= 1e-9

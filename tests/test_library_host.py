@@ -161,3 +161,25 @@ def test_transfer_tables_match_oracle_integrals(p):
         want = np.linalg.solve(M, V)
         got = d.sld_ref_operator("Ldm", alpha).reshape(N, N)
         assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+
+
+def test_host_only_handle_refuses_imex_entry_points():
+    """A host-only disc (device -1) has no device state: the transfer, diffusion and state
+    entry points refuse it with SLD_E_INVALID before touching any pointer."""
+    import ctypes
+    from paper_2401_17806_amd import sld
+    xy, tri, per = lattice_mesh(3, seed=1)
+    d = sld.Disc(sld.Mesh(xy, tri, per, device=-1), 2)
+    lib = sld._lib
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.sld_dual_to_main(d.handle, fake, 2, ctypes.c_void_p(0x2000), None) == 1
+    assert "host-only" in sld.sld_last_error()
+    assert lib.sld_main_to_dual(d.handle, fake, 2, ctypes.c_void_p(0x2000), None) == 1
+    prm = sld.make_params()
+    assert lib.sld_viscous_solve(d.handle, fake, 0.1, None, None, ctypes.c_void_p(0x2000),
+                                 ctypes.byref(prm), None, None) == 1
+    h = ctypes.c_void_p()
+    assert lib.sld_state_create(d.handle, ctypes.byref(h)) == 1 and not h.value
+    # argument checks come first
+    assert lib.sld_dual_to_main(d.handle, fake, 9, ctypes.c_void_p(0x2000), None) == 1
+    assert "nc" in sld.sld_last_error()
