@@ -411,14 +411,39 @@ __device__ __forceinline__ void lds_scatter(double* slot_base /* [4][N] of this 
     for (int k = 0; k < N; ++k) slot_base[al * N + rot_sel<P>(al, k)] = y[k];
 }
 
+// Lane data movement of a float64 within a wave through DPP (no memory access).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of a wave, the same in every lane: pairs and quads (quad permutes),
+// then the four quads of each row of 16 lanes (rotations by 4 and 8), then the four rows' sums
+// read from lanes 0, 16, 32, 48.  Fixed order, bitwise identical in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x124>(v);  // row_ror:4
+    v += dpp_f64<0x128>(v);  // row_ror:8
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // Deterministic block sum of NV values; result returned in every thread.
 template <int NV, int NT>
 __device__ __forceinline__ void block_sum_all(double (&v)[NV]) {
     __shared__ double sh[NV][NT / 64];
 #pragma unroll
-    for (int c = 0; c < NV; ++c)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off);
+    for (int c = 0; c < NV; ++c) v[c] = wave_sum(v[c]);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0)
