@@ -1,5 +1,6 @@
-"""Serving loop for the pressure solve: a stream of independent requests on meshes of different
-sizes and degrees, run through the library's continuous-batching server (sld_server_*).
+"""Serving loop for the pressure solve and the IMEX step: a stream of independent requests on
+meshes of different sizes and degrees, run through the library's continuous-batching server
+(sld_server_*).
 
 Each request is (mesh n, degree p, precision, seed): the pressure stage right-hand side
 b = D v* of a seeded Gaussian random Fourier velocity field v* (|k| <= kmax, amplitude ~ |k|^-2)
@@ -9,6 +10,10 @@ meshes).  Every request brings its own jittered mesh (seed =
 request seed).  On arrival it is set up on the device (mesh tables, discretisation, right-hand
 side) as soon as the device-memory budget allows, submitted to the server, and freed when its
 result is in.  Latency = arrival -> result ready on the host, setup included.
+
+A fraction of the requests (imex_fraction) can be IMEX steps instead: one R = 0
+semi-Lagrangian IMEX step of the Taylor-Green vortex (nu = 1e-2, dt = 0.5 h) on the request's
+mesh, its velocity interpolated at the dual nodes, the pressure solved to the same tolerance.
 """
 from __future__ import annotations
 
@@ -23,13 +28,17 @@ from .inputs import lattice_mesh
 
 
 def request_mix(nreq: int, seed: int, sizes=(16, 32, 64, 128, 256), degrees=(1, 2, 3, 4),
-                mixed_fraction: float = 0.5):
-    """Seeded heterogeneous request list: n and p uniform, FP64/mixed by a Bernoulli draw."""
+                mixed_fraction: float = 0.5, imex_fraction: float = 0.0):
+    """Seeded heterogeneous request list: n and p uniform, FP64/mixed by a Bernoulli draw, IMEX
+    step or pressure solve by a second Bernoulli draw (its own stream, so the solve mix does
+    not depend on imex_fraction)."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    kind_rng = np.random.Generator(np.random.PCG64(seed + 7))
     out = []
     for r in range(nreq):
         out.append({"id": r, "n": int(rng.choice(sizes)), "p": int(rng.choice(degrees)),
                     "precision": "mixed" if rng.random() < mixed_fraction else "fp64",
+                    "kind": "imex" if kind_rng.random() < imex_fraction else "solve",
                     "seed": 1000 + r})
     return out
 
@@ -66,6 +75,14 @@ def _rhs(disc, seed, kmax, torch):
         for comp in range(2):
             v[:, comp].add_(c, alpha=float(ca[m, comp])).add_(sn, alpha=float(cb[m, comp]))
     return disc.sld_pressure_rhs(v, 1.0)
+
+
+def _tgv_dual(disc, torch):
+    """Taylor-Green velocity [nd, 2, Npsi] interpolated at the dual nodes (t = 0)."""
+    x = disc.dual_nodes()
+    u = np.stack([np.sin(x[..., 0]) * np.cos(x[..., 1]),
+                  -np.cos(x[..., 0]) * np.sin(x[..., 1])], axis=1)
+    return torch.from_numpy(np.ascontiguousarray(u)).to(f"cuda:{disc.mesh.device}")
 
 
 def run(requests, arrivals, *, workers=4, budget_bytes=32 << 30, rtol=1e-12,
@@ -109,20 +126,32 @@ def _run(torch, requests, arrivals, workers, budget_bytes, rtol, mixed_rtol, kma
             xy, tri, per = q["mesh"]
             mesh = sld.Mesh(xy, tri, per, device=0)
             disc = sld.Disc(mesh, q["p"])
-            fb = disc.footprint()
-            footprint[key] = fb
-            resident += fb
-            b = _rhs(disc, q["seed"], kmax, torch)
-            p = torch.empty_like(b)
             tol = mixed_rtol if q["precision"] == "mixed" else rtol
-            t = server.sld_server_submit(disc, b, p, rtol=tol, precision=q["precision"],
-                                         graph_block=graph_block, maxit=200000)
-            inflight[t] = (r, disc, mesh, p, fb)
+            state = None
+            if q.get("kind", "solve") == "imex":
+                state = sld.State(disc)
+                # the state's workspace and the request's velocity and pressure
+                fb = disc.footprint() + 8 * (8 * mesh.ne * disc.nphi + 3 * mesh.nd * disc.npsi)
+                v = _tgv_dual(disc, torch)
+                p = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+                t = server.sld_server_submit_imex(state, v, p, 0.5 * 2 * np.pi / q["n"], 1e-2,
+                                                  rtol=tol, precision=q["precision"],
+                                                  graph_block=graph_block, maxit=200000,
+                                                  warm_start=False)
+            else:
+                fb = disc.footprint()
+                b = _rhs(disc, q["seed"], kmax, torch)
+                p = torch.empty_like(b)
+                t = server.sld_server_submit(disc, b, p, rtol=tol, precision=q["precision"],
+                                             graph_block=graph_block, maxit=200000)
+            footprint[key] = max(footprint.get(key, 0), fb)
+            resident += fb
+            inflight[t] = (r, disc, mesh, p, fb, state)
         for t in list(inflight):
             rep = server.sld_server_poll(t)
             if rep is None:
                 continue
-            r, disc, mesh, p, fb = inflight.pop(t)
+            r, disc, mesh, p, fb, state = inflight.pop(t)
             done = time.perf_counter() - t0
             q = requests[r]
             records[r] = {k: v for k, v in q.items() if k != "mesh"}
@@ -131,6 +160,8 @@ def _run(torch, requests, arrivals, workers, budget_bytes, rtol, mixed_rtol, kma
                               status=rep["status"], rel_res_true=rep["rel_res_true"],
                               dofs=disc.mesh.ne * disc.nphi,
                               solution=p if keep_solutions else None)
+            if state is not None:
+                state.close()
             disc.close()
             mesh.close()
             resident -= fb
@@ -160,6 +191,13 @@ def summarize(records, wall):
         if len(lp):
             out[f"{pr}_latency_ms_p50"] = float(np.percentile(lp, 50) * 1e3)
             out[f"{pr}_latency_ms_p99"] = float(np.percentile(lp, 99) * 1e3)
+    kinds = collections.Counter(r.get("kind", "solve") for r in records)
+    if len(kinds) > 1:
+        for kd in kinds:
+            lk = np.array([r["latency"] for r in records if r.get("kind", "solve") == kd])
+            out[f"{kd}_requests"] = int(len(lk))
+            out[f"{kd}_latency_ms_p50"] = float(np.percentile(lk, 50) * 1e3)
+            out[f"{kd}_latency_ms_p99"] = float(np.percentile(lk, 99) * 1e3)
     return out
 
 
@@ -176,15 +214,20 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--imex-fraction", type=float, default=0.0,
+                    help="share of the requests that are IMEX steps instead of pressure solves")
     a = ap.parse_args(argv)
     sizes = tuple(int(x) for x in a.sizes.split(","))
     degrees = tuple(int(x) for x in a.degrees.split(","))
-    reqs = request_mix(a.requests, a.seed, sizes=sizes, degrees=degrees)
+    reqs = request_mix(a.requests, a.seed, sizes=sizes, degrees=degrees,
+                       imex_fraction=a.imex_fraction)
     budget = int(a.budget_gib * (1 << 30))
     prepare(reqs)
     # warm pass: load the kernels of every degree and precision once, on the smallest mesh
-    warm = [{"id": k, "n": min(sizes), "p": p, "precision": pr, "seed": 900 + k}
-            for k, (p, pr) in enumerate((p, pr) for p in degrees for pr in ("fp64", "mixed"))]
+    kinds = ("solve", "imex") if a.imex_fraction > 0 else ("solve",)
+    warm = [{"id": k, "n": min(sizes), "p": p, "precision": pr, "kind": kd, "seed": 900 + k}
+            for k, (p, pr, kd) in enumerate((p, pr, kd) for p in degrees
+                                            for pr in ("fp64", "mixed") for kd in kinds)]
     run(warm, None, workers=a.workers, budget_bytes=budget)
     recs, wall = run(reqs, None, workers=a.workers, budget_bytes=budget, progress=32)
     closed = summarize(recs, wall)

@@ -177,3 +177,34 @@ def test_server_imex_steps_equal_direct_steps(torch_dev):
         assert torch.equal(vs[k], alone_v[k]) and torch.equal(ps[k], alone_p[k]), k
     for k in range(len(sdiscs)):
         assert torch.equal(xs[k], alone_x[k]), k
+
+
+def test_serving_loop_with_imex_requests(torch_dev):
+    """The serving loop with half of the requests IMEX steps: every request ends SLD_OK, and each
+    served IMEX step's pressure equals the same step run alone, bitwise."""
+    torch = torch_dev
+    from paper_2401_17806_amd import serve, sld
+    _say("[serve] poisson loop with imex steps")
+    reqs = serve.request_mix(12, seed=8, sizes=(8, 12), degrees=(1, 2, 3), imex_fraction=0.5)
+    assert 0 < sum(q["kind"] == "imex" for q in reqs) < len(reqs)
+    arr = serve.poisson_arrivals(len(reqs), rate=200.0, seed=9)
+    recs, wall = serve.run(reqs, arr, workers=3, keep_solutions=True, kmax=4)
+    summ = serve.summarize(recs, wall)
+    _say("   ", summ)
+    assert summ["statuses"] == {"SLD_OK": len(reqs)}
+    side = torch.cuda.Stream(device=0)
+    with torch.cuda.stream(side):
+        for q, rec in zip(reqs, recs):
+            if q["kind"] != "imex":
+                continue
+            mesh = sld.Mesh(*q["mesh"], device=0)
+            disc = sld.Disc(mesh, q["p"])
+            st = sld.State(disc)
+            v = serve._tgv_dual(disc, torch)
+            p = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
+            tol = 1e-10 if q["precision"] == "mixed" else 1e-12
+            rep = st.sld_imex_step(v, p, 0.5 * 2 * np.pi / q["n"], 1e-2, rtol=tol,
+                                   precision=q["precision"], graph_block=32, maxit=200000,
+                                   warm_start=False)
+            assert rep["status"] == "SLD_OK"
+            assert torch.equal(p, rec["solution"]), q["id"]
