@@ -376,6 +376,8 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: FP32 CG with FP64 reliable updates (true FP64 residual to rtol)")
     ap.add_argument("--graph-block", type=int, default=64)
+    ap.add_argument("--inner-rtol", type=float, default=0.5,
+                    help="mixed: residual reduction of the FP32 process between FP64 refreshes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sl-advect", action="store_true",
                     help="measure the semi-Lagrangian advection kernel instead (3 fields, CFL 0.5)")
@@ -439,7 +441,7 @@ def main():
         disc.sld_pressure_rhs(vstar, 1.0 / coef, out=b)
         _, rep = disc.sld_cg_solve(b, p=pres, rtol=args.rtol, graph_block=args.graph_block,
                                    profile=profile and not mixed, precision=args.precision,
-                                   maxit=200000)
+                                   inner_rtol=args.inner_rtol, maxit=200000)
         disc.sld_velocity_correct(vstar, pres, coef, out=vnew)
         return rep
 
