@@ -244,7 +244,10 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
         const int64_t base = i0 * N;
         // phase 1: state update of the tile (coalesced) and directions of tile + halo into LDS
         if constexpr (kFront) {
-            // the loads were issued at entry
+            // the loads were issued at entry.  The state is stored non-temporally: the next
+            // launch reads it after the kernel boundary (from the memory-side cache, never from
+            // this XCD's L2), and streaming stores were measured 3% faster per iteration on a
+            // 128x128x2, p = 3 mesh
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const int f = threadIdx.x + u * NT;
@@ -252,9 +255,9 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
                     const int64_t o = base + f;
                     const Real rk = mad(-ra, vq[u], vr[u]);
                     const Real dk = mad(rb, vd[u], rk);
-                    x[o] = mad(ra, vd[u], vx[u]);
-                    r_out[o] = rk;
-                    d_out[o] = dk;
+                    __builtin_nontemporal_store(mad(ra, vd[u], vx[u]), &x[o]);
+                    __builtin_nontemporal_store(rk, &r_out[o]);
+                    __builtin_nontemporal_store(dk, &d_out[o]);
                     sd[f] = dk;
                     sr[f] = rk;
                     acc[0] = fma((double)rk, (double)rk, acc[0]);
@@ -421,7 +424,8 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
             Real qk = (sm[(t * R) * N + k] + sm[(t * R + 1) * N + k]) + sm[(t * R + 2) * N + k];
             if constexpr (R == 4) qk += sm[(t * R + 3) * N + k];
             qk = -qk;
-            q_out[base + f] = qk;
+            if constexpr (kFront) __builtin_nontemporal_store(qk, &q_out[base + f]);
+            else q_out[base + f] = qk;
             const double dk = sd[f], rk = sr[f], qd = qk;
             acc[1] = fma(dk, qd, acc[1]);
             acc[2] = fma(rk, qd, acc[2]);
