@@ -9,6 +9,7 @@
 #include <string>
 #include <unordered_map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "sld_internal.h"
@@ -619,7 +620,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
                           hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&w.capture, hipStreamNonBlocking);
     if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), CgScalars::NSCAL * sizeof(double),
+        e = hipHostMalloc(reinterpret_cast<void**>(&w.host_scal), 3 * CgScalars::NSCAL * sizeof(double),
                           hipHostMallocDefault);
     if (e != hipSuccess) {
         free_disc(d);
@@ -870,43 +871,88 @@ struct IterStats {
     double t_step = 0;
 };
 
-// Run CG iterations until the device flags DONE in `scal` (host mirror `hs`).
+// Run CG iterations until the device flags DONE in `scal`.  `hs` is pinned host memory of
+// 3 NSCAL doubles: the final scalars land in hs[0, NSCAL), and two copy slots follow.
+//
+// Each graph block of gb launches is followed by a copy of the scalars into its slot, which the
+// host reads to decide whether to go on.  While the previous solve of the same kind on this disc
+// says at least two more blocks are needed, the host queues the next block before reading the
+// current one, so the device does not idle during the read (the fewest blocks of the last three
+// solves of that kind: the viscous and temperature solves of a step share the kind).  A block queued after convergence
+// only runs launches that exit at entry, and results do not depend on the queueing.
 sld_status run_iterations(sld_disc_s* d, bool fp32, bool shift, int gb, bool prof, hipStream_t s,
                           double* scal, double* hs, IterStats* st) {
     typedef CgScalars S;
     CgWork& w = d->cg;
     hipGraphExec_t& graph = fp32 ? w.graph32 : (shift ? w.graph_shift : w.graph);
     int& graph_block = fp32 ? w.graph32_block : (shift ? w.graph_shift_block : w.graph_block);
-    if (prof && w.events.size() < 2) {
+    // events: profile start / end of each slot's block, then each slot's copy
+    if (w.events.size() < 6) {
         for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
-        w.events.assign(2, nullptr);
+        w.events.assign(6, nullptr);
         for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
     }
     if (graph == nullptr || graph_block != gb) {
         SLD_HIP_CHECK(capture_block(d, fp32, shift, gb, &graph));
         graph_block = gb;
     }
-    int launched = 0;
+    const int kind = shift ? 1 : 0;
+    int expect = 0;  // fewest blocks among the recorded solves (0: none recorded)
+    if (!fp32 && w.last_gb[kind] == gb)
+        for (int h = 0; h < 3; ++h)
+            if (w.last_blocks[kind][h] > 0 && (expect == 0 || w.last_blocks[kind][h] < expect))
+                expect = w.last_blocks[kind][h];
+    double* slot[2] = {hs + S::NSCAL, hs + 2 * S::NSCAL};
+    auto enqueue = [&](int b) -> hipError_t {
+        const int k = b & 1;
+        hipError_t e = hipSuccess;
+        if (prof) e = hipEventRecord(w.events[2 * k], s);
+        if (e == hipSuccess) e = hipGraphLaunch(graph, s);
+        if (prof && e == hipSuccess) e = hipEventRecord(w.events[2 * k + 1], s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(slot[k], scal, S::NSCAL * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(w.events[4 + k], s);
+        return e;
+    };
+    int launched = 0, queued = 0, read = 0;
+    SLD_HIP_CHECK(enqueue(queued++));
     while (true) {
-        // profile: HIP events on the solve stream around each captured block of gb launches
-        if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[0], s));
-        SLD_HIP_CHECK(hipGraphLaunch(graph, s));
-        if (prof) SLD_HIP_CHECK(hipEventRecord(w.events[1], s));
-        SLD_HIP_CHECK(hipMemcpyAsync(hs, scal, S::NSCAL * sizeof(double), hipMemcpyDeviceToHost, s));
-        SLD_HIP_CHECK(hipStreamSynchronize(s));
-        st->done = (int)hs[S::DONE];
+        // run one block ahead while the previous solve needed at least two more blocks
+        if (queued == read + 1 && queued + 1 < expect) SLD_HIP_CHECK(enqueue(queued++));
+        const int k = read & 1;
+        // wait for this block's copy (polled, as a stream synchronisation spins)
+        hipError_t q;
+        while ((q = hipEventQuery(w.events[4 + k])) == hipErrorNotReady) std::this_thread::yield();
+        SLD_HIP_CHECK(q);
+        const double* h = slot[k];
+        ++read;
+        st->done = (int)h[S::DONE];
         const int before = launched;
         // launches that did work: the counter of the slot written last
-        launched = (int)std::max(hs[S::ITER0], hs[S::ITER1]);
-        st->iters = st->done ? (int)hs[S::ITER] : launched - 1;
+        launched = (int)std::max(h[S::ITER0], h[S::ITER1]);
+        st->iters = st->done ? (int)h[S::ITER] : launched - 1;
         if (prof && launched - before == gb) {
-            // only blocks whose launches all iterated (the last block of a solve exits early)
+            // profile: HIP events on the solve stream around each captured block of gb
+            // launches, for blocks whose launches all iterated (the last block exits early)
             float a = 0;
-            SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[0], w.events[1]));
+            SLD_HIP_CHECK(hipEventElapsedTime(&a, w.events[2 * k], w.events[2 * k + 1]));
             st->t_step += a;
             st->timed += gb;
         }
-        if (st->done) return SLD_OK;
+        if (st->done) {
+            std::memcpy(hs, h, S::NSCAL * sizeof(double));
+            if (!fp32) {
+                if (w.last_gb[kind] != gb) {
+                    for (int h = 0; h < 3; ++h) w.last_blocks[kind][h] = 0;
+                    w.last_gb[kind] = gb;
+                }
+                w.last_blocks[kind][2] = w.last_blocks[kind][1];
+                w.last_blocks[kind][1] = w.last_blocks[kind][0];
+                w.last_blocks[kind][0] = read;
+            }
+            return SLD_OK;
+        }
+        if (queued == read) SLD_HIP_CHECK(enqueue(queued++));
     }
 }
 

@@ -70,13 +70,17 @@ struct CgWork {
     double* part = nullptr;        // [2][4][grid] partials of rr, dq, rq, qq (by parity)
     double* part_s = nullptr;      // [2][grid] partials of setup / finish reductions
     double* scal = nullptr;        // device scalars (CgScalars)
-    double* host_scal = nullptr;   // pinned mirror of scal
+    double* host_scal = nullptr;   // pinned mirror of scal, then two block copy slots
     int grid = 0;                  // blocks of every CG kernel
     bool front = false;            // iteration kernel variant: one tile per block, four roles
     int stream_x = -1;             // x with non-temporal accesses: -1 by working-set size, 0/1
     unsigned char* wall_i = nullptr;  // [ne] internal order: Dirichlet wall edges (bit per local
                                       // edge) of the current diffusion solve
-    std::vector<hipEvent_t> events;  // profiling events (created on first profiled solve)
+    std::vector<hipEvent_t> events;  // block profiling and copy events (created on first solve)
+    // graph blocks the last three FP64 solves of each kind (pressure, viscous) ran, newest
+    // first, at graph size last_gb: how far the host may queue blocks ahead of its reads
+    int last_blocks[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    int last_gb[2] = {0, 0};
     // mixed precision: FP32 inner CG state (e32 = the correction), its partials and scalars
     float* r32[2] = {nullptr, nullptr};
     float* q32[2] = {nullptr, nullptr};
