@@ -162,6 +162,36 @@ def test_cg_deterministic_and_warm_start(torch_dev):
     assert r3["iters"] <= 2 and _rel(p3.cpu().numpy(), p1.cpu().numpy()) < 1e-9
 
 
+def test_cg_blocks_queued_ahead(torch_dev):
+    """Once a disc has solved, the host queues the next graph block before reading the current
+    one; a block queued past convergence (a solve much shorter than the ones before it) must
+    change neither that solve nor the next one."""
+    torch = torch_dev
+    from paper_2401_17806_amd import sld
+    _say("[cg run-ahead] n=12 p=2 graph_block=2")
+    xy, tri, per = lattice_mesh(12, seed=5, periodic=True, length=2 * np.pi)
+
+    def fresh():
+        return sld.Disc(sld.Mesh(xy, tri, per, device=0), 2)
+
+    disc = fresh()
+    od = OracleDisc(OracleMesh(xy, tri, per), 2)
+    b = solve.project_mean(random_vector((disc.mesh.ne, disc.nphi), seed=53))
+    xref = solve.gauge(od, solve.dense_bordered_solve(solve.assemble_K(od), b))
+    bt = _to(torch, b)
+    p0, r0 = fresh().sld_cg_solve(bt, rtol=1e-12, graph_block=2)  # no history: no run-ahead
+    assert r0["iters"] > 20 and _rel(p0.cpu().numpy(), xref) <= SOLVE_TOL
+    for k in range(3):  # the second and third solves run ahead
+        pk, rk = disc.sld_cg_solve(bt, rtol=1e-12, graph_block=2)
+        assert torch.equal(pk, p0) and rk["iters"] == r0["iters"], k
+    # warm start from the solution: done in the first block, with a second block queued
+    pw0, rw0 = fresh().sld_cg_solve(bt, p=p0.clone(), rtol=1e-8, warm_start=True, graph_block=2)
+    pw, rw = disc.sld_cg_solve(bt, p=p0.clone(), rtol=1e-8, warm_start=True, graph_block=2)
+    assert torch.equal(pw, pw0) and rw["iters"] == rw0["iters"] and rw["converged"]
+    p4, r4 = disc.sld_cg_solve(bt, rtol=1e-12, graph_block=2)
+    assert torch.equal(p4, p0) and r4["iters"] == r0["iters"]
+
+
 def test_cg_nonconvergence_is_reported(torch_dev):
     torch = torch_dev
     _say("[cg maxit] n=12 p=2")
