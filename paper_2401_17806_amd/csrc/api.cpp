@@ -842,7 +842,8 @@ sld_status sld_sl_advect(sld_disc d, const double* vbar, const double* q, int32_
 namespace {
 
 // Capture one block of gb CG iterations (FP64, FP64 mass-shifted, or the FP32 inner solve)
-// into a graph.
+// into a graph.  The FP32 block ends with the peek at its process's recursive rr, so that the
+// host reads the stop flag and that rr from one copy of the scalars.
 hipError_t capture_block(sld_disc_s* d, bool fp32, bool shift, int gb, hipGraphExec_t* out) {
     CgWork& w = d->cg;
     if (*out) {
@@ -858,6 +859,7 @@ hipError_t capture_block(sld_disc_s* d, bool fp32, bool shift, int gb, hipGraphE
     for (int k = 0; k < gb && ce == hipSuccess; ++k)
         ce = fp32 ? launch_cg_step32(d, k & 1, w.capture)
                   : launch_cg_step(d, k & 1, shift, w.capture);
+    if (fp32 && ce == hipSuccess) ce = launch_rel_peek(d, 0, w.capture);
     e = hipStreamEndCapture(w.capture, &g);
     if (ce != hipSuccess) return ce;
     if (e != hipSuccess) return e;
@@ -1032,10 +1034,7 @@ sld_status cg_solve_impl(sld_disc d, const double* b, double* p, const sld_cg_pa
                 sld_status e = run_block(d, prm->graph_block, s, &in);
                 if (e != SLD_OK) return e;
                 if (in.done || base + in.iters >= prm->maxit) break;
-                SLD_HIP_CHECK(launch_rel_peek(d, 0, s));
-                SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal_in, w.scal_in, S::NSCAL * sizeof(double),
-                                             hipMemcpyDeviceToHost, s));
-                SLD_HIP_CHECK(hipStreamSynchronize(s));
+                // (the block's graph ended with the peek: RRNOW is current)
                 if (w.host_scal_in[S::RRNOW] <= refresh * refresh * rr_ref) break;
             }
             total = base + in.iters;
