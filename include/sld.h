@@ -174,14 +174,17 @@ sld_status sld_sl_advect(sld_disc disc, const double* vbar, const double* q, int
  *   int_Omega p dx = 0.
  * Stopping rule: ||r_k||_2 <= rtol ||b||_2 on coefficient vectors; the true residual is
  * recomputed at exit.  Iterations run as a captured HIP graph of graph_block iterations
- * (scalars stay on the device); the calling thread blocks until the solve ends and
- * synchronises `stream` once per graph to test convergence.  Results are deterministic
- * (fixed-order reductions, no atomics).  On SLD_E_NOCONV p holds
- * the last iterate and the report is filled. */
+ * (scalars stay on the device); the calling thread blocks until the solve ends and reads the
+ * scalars copied after each graph to test convergence.  From the second FP64 solve of a kind
+ * (pressure or viscous) on a disc, the next graph is queued on `stream` before the current
+ * one's scalars are read, while the disc's recent solves predict two more graphs; a graph
+ * queued after convergence runs only launches that exit at entry.  Results are deterministic
+ * (fixed-order reductions, no atomics) and do not depend on that queueing.  On SLD_E_NOCONV p
+ * holds the last iterate and the report is filled. */
 typedef struct {
     double rtol;          /* relative residual tolerance, e.g. 1e-12 (FP64) / 1e-11 (mixed) */
     double inner_rtol;    /* mixed only: reduction of the FP32 residual between two FP64
-                             reliable updates (refreshes of x and of the true residual), e.g. 0.3 */
+                             reliable updates (refreshes of x and of the true residual), e.g. 0.5 */
     int32_t maxit;        /* iteration cap (mixed: per inner solve) */
     int32_t warm_start;   /* nonzero: p holds the initial guess */
     int32_t graph_block;  /* iterations per convergence check (even, 2..4096) */
