@@ -375,7 +375,10 @@ def main():
                     help="CG tolerance (default 1e-12 FP64, 1e-11 mixed)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: FP32 CG with FP64 reliable updates (true FP64 residual to rtol)")
-    ap.add_argument("--graph-block", type=int, default=64)
+    ap.add_argument("--graph-block", type=int, default=None,
+                    help="CG iterations per captured graph (convergence check): default 256 for "
+                         "the pressure solve, 64 for --imex / --cavity, whose short viscous "
+                         "solves would run more launches past convergence")
     ap.add_argument("--inner-rtol", type=float, default=0.5,
                     help="mixed: residual reduction of the FP32 process between FP64 refreshes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -391,6 +394,8 @@ def main():
                          "(reference kernel for HBM byte counters)")
     args = ap.parse_args()
     args.precision_given = any(a.startswith("--precision") for a in sys.argv[1:])
+    if args.graph_block is None:
+        args.graph_block = 64 if (args.imex or args.cavity) else 256
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}); the "
               "multi-GPU sharding of the pressure solve is a design note, not a measured path",
