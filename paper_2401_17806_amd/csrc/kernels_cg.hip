@@ -132,10 +132,12 @@ inline size_t step_lds_bytes(int nphi, int hmax, size_t real_bytes, bool front) 
            (size_t)(kTriPerBlock + hmax + kTriPerBlock + (front ? 4 : 3) * kTriPerBlock);
 }
 
-// kFront: the grid has one tile per block (cache-resident meshes, latency-bound).  Every load
-// that does not depend on alpha and beta -- the tile's state, its halo ids, the previous
-// launch's dot partials and the scalars -- is issued at entry, so their latencies overlap;
-// otherwise (several tiles per block) the loads follow the tile loop.
+// kFront: the grid has one tile per block (cache-resident meshes, latency-bound).  The tile's
+// state and its halo ids are requested at entry, together with the scalars; the previous
+// launch's dot partials follow as soon as the iteration scalar shows there are any, so these
+// latencies overlap (requesting more at entry -- the halo values, the phase-2 geometry, the
+// partials unconditionally -- measured slower).  With several tiles per block the loads follow
+// the tile loop.
 template <int P, typename Real, class Ops, bool kFront, bool kShift, bool kStream>
 __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const Ops* __restrict__ ops,
                                                        const double4* __restrict__ geo,
