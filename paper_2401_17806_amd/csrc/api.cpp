@@ -79,6 +79,7 @@ void free_mesh(sld_mesh_s* m) {
     dfree(m->halo_pad);
     dfree(m->perm);
     dfree(m->geo_i);
+    dfree(m->geo_nb);
     dfree(m->nbr_i);
     delete m;
 }
@@ -419,6 +420,14 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
             for (int al = 0; al < 3; ++al) v[al] = v[al] < 0 ? -1 : pack_nbr(inv[v[al] >> 2], v[al] & 3);
             nbr_i[i] = make_int4(v[0], v[1], v[2], 0);
         }
+        // the neighbour's geometry across each local edge (zeros on a wall), so that the CG
+        // iteration reads it without first reading the neighbour's id
+        std::vector<double4> geo_nb(size_t(ne) * 3);
+        for (int64_t i = 0; i < ne; ++i) {
+            const int v[3] = {nbr_i[i].x, nbr_i[i].y, nbr_i[i].z};
+            for (int al = 0; al < 3; ++al)
+                geo_nb[size_t(i) * 3 + al] = v[al] < 0 ? make_double4(0, 0, 0, 0) : geo_i[v[al] >> 2];
+        }
         // tiles of kTriPerBlock consecutive (internal) triangles: halo lists and local slots
         const int64_t ntiles = (ne + kTriPerBlock - 1) / kTriPerBlock;
         std::vector<int> halo_off(ntiles + 1, 0), halo_ids;
@@ -487,11 +496,13 @@ sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int
         if (e == hipSuccess) e = dalloc(&m->edges, m->nd);
         if (e == hipSuccess) e = dalloc(&m->perm, ne);
         if (e == hipSuccess) e = dalloc(&m->geo_i, ne);
+        if (e == hipSuccess) e = dalloc(&m->geo_nb, size_t(ne) * 3);
         if (e == hipSuccess) e = dalloc(&m->nbr_i, ne);
         if (e == hipSuccess) e = dalloc(&m->halo_pad, halo_pad.size());
         if (e == hipSuccess) {
             up.copy(m->perm, perm.data(), sizeof(int) * ne);
             up.copy(m->geo_i, geo_i.data(), sizeof(double4) * ne);
+            up.copy(m->geo_nb, geo_nb.data(), sizeof(double4) * geo_nb.size());
             up.copy(m->nbr_i, nbr_i.data(), sizeof(int4) * ne);
             up.copy(m->halo_pad, halo_pad.data(), sizeof(int) * halo_pad.size());
             up.copy(m->geo, geo.data(), sizeof(double4) * ne);

@@ -48,6 +48,8 @@ struct sld_mesh_s {
     // consecutive triangles are compact patches with small halos):
     int* perm = nullptr;           // [ne] internal index -> caller's triangle index
     double4* geo_i = nullptr;      // [ne] geo in internal order
+    double4* geo_nb = nullptr;     // [ne][3] internal order: geo_i of the neighbour across local
+                                   // edge alpha (zeros on a wall)
     int4* nbr_i = nullptr;         // [ne] internal neighbour ids (packed as nbr); w = the three
                                    // tile-local slots (10 bits each): 0..63 own tile, 64+h halo
     int* halo_pad = nullptr;       // [ntiles][max(hmax, 1)] halo triangles (internal ids) of
