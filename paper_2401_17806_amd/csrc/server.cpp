@@ -135,7 +135,9 @@ sld_status sld_disc_footprint(sld_disc d, uint64_t* bytes) {
         sld_set_error("sld_disc_footprint: NULL argument");
         return SLD_E_INVALID;
     }
-    *bytes = sld_disc_bytes(d) + uint64_t(d->mesh->ne) * 96;  // + geometry and tables
+    // + the mesh tables per triangle: geo, geo_i (32 B each), geo_nb (96 B), nbr, nbr_i, tedges
+    // (16 B each), perm (4 B), the padded halo lists (a few B), the wall flags (1 B)
+    *bytes = sld_disc_bytes(d) + uint64_t(d->mesh->ne) * 224;
     return SLD_OK;
 }
 
