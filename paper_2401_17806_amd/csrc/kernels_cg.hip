@@ -105,6 +105,36 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
 
 // The previous launch's G partials of the four CG dots, summed in a fixed order (every block
 // gets bitwise the same totals); four partials per thread and dot are in flight at a time.
+// The same sum with its first pass (partials threadIdx.x + u NT, u < 4) requested ahead of it;
+// the order of the additions is the same.
+template <int NT>
+struct DotPartials {
+    double w[4][4];
+    __device__ __forceinline__ void load(const double* __restrict__ part_in, int G, int b0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u * NT;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) w[u][c] = b < G ? part_in[c * G + b] : 0.0;
+        }
+    }
+    __device__ __forceinline__ void add(double (&v)[4]) const {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] += w[u][c];
+    }
+    // v = the totals, given the first pass loaded
+    __device__ __forceinline__ void sum(const double* __restrict__ part_in, int G, double (&v)[4]) {
+        add(v);
+        for (int b0 = threadIdx.x + 4 * NT; b0 < G; b0 += 4 * NT) {
+            load(part_in, G, b0);
+            add(v);
+        }
+        block_sum_all<4, NT>(v);
+    }
+};
+
 template <int NT>
 __device__ __forceinline__ void sum_dot_partials(const double* __restrict__ part_in, int G,
                                                  double (&v)[4]) {
@@ -205,7 +235,14 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
             hid[u] = e < nhe ? halo_pad[tile * hs + e / N] : -1;
         }
     };
+    // FP32 state, one tile per block: the dot partials are requested first (whatever the
+    // iteration count; unused on the first launch), since loads return in order and the sum
+    // then need not wait for the tile's state.  Measured on a 128x128x2, p = 3 mesh: 2% faster
+    // per FP32 iteration, but 4% slower per FP64 one, which keeps the order below.
+    constexpr bool kEarlyPartials = kFront && sizeof(Real) == 4;
+    DotPartials<NT> dp;
     if constexpr (kFront) {
+        if constexpr (kEarlyPartials) dp.load(part_in, G, threadIdx.x);
         if (t_begin < t_end) {
             load_own(t_begin);
             load_hid(t_begin, 0);
@@ -216,7 +253,8 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
     double alpha = 0.0, beta = 0.0;
     if (it > 0.0) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
-        sum_dot_partials<NT>(part_in, G, v);
+        if constexpr (kEarlyPartials) dp.sum(part_in, G, v);
+        else sum_dot_partials<NT>(part_in, G, v);
         const double rr = v[0], dq = v[1], rq = v[2], qq = v[3];
         if (done != 0.0) return;
         // every block takes the same decision from the same sums
