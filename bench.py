@@ -377,8 +377,9 @@ def main():
                     help="mixed: FP32 CG with FP64 reliable updates (true FP64 residual to rtol)")
     ap.add_argument("--graph-block", type=int, default=None,
                     help="CG iterations per captured graph (convergence check): default 256 for "
-                         "the pressure solve, 64 for --imex / --cavity, whose short viscous "
-                         "solves would run more launches past convergence")
+                         "the pressure solve; for --imex / --cavity, whose short viscous solves "
+                         "would run more launches past convergence, 128 on meshes of n >= 64 "
+                         "and 64 below")
     ap.add_argument("--inner-rtol", type=float, default=0.5,
                     help="mixed: residual reduction of the FP32 process between FP64 refreshes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -394,8 +395,13 @@ def main():
                          "(reference kernel for HBM byte counters)")
     args = ap.parse_args()
     args.precision_given = any(a.startswith("--precision") for a in sys.argv[1:])
+    if args.cavity and not any(a.startswith("--workload") for a in sys.argv[1:]):
+        args.workload = "cavity256_p2"
     if args.graph_block is None:
-        args.graph_block = 64 if (args.imex or args.cavity) else 256
+        if args.imex or args.cavity:
+            args.graph_block = 128 if WORKLOADS[args.workload]["n"] >= 64 else 64
+        else:
+            args.graph_block = 256
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}); the "
               "multi-GPU sharding of the pressure solve is a design note, not a measured path",
@@ -410,8 +416,6 @@ def main():
         bench_sl_advect(args, torch, sld, lattice_mesh, random_fourier_field)
         return
     if args.cavity:
-        if not any(a.startswith("--workload") for a in sys.argv[1:]):
-            args.workload = "cavity256_p2"
         if not WORKLOADS[args.workload].get("walls"):
             sys.exit("--cavity runs the walled workloads")
         bench_cavity(args, torch, sld, lattice_mesh)
