@@ -84,3 +84,192 @@ def test_walk_lands_on_the_straight_line_foot():
             assert np.abs(k - np.round(k)).max() <= 1e-9
             crossings += steps - 1
     assert crossings > 50
+
+
+# ---------------------------------------------------------------------------------------------
+# Velocity that varies from cell to cell (Section 3.5: each straight segment takes the velocity
+# of the cell it runs in).  These pins separate the oracle's per-cell rule from a walk that keeps
+# the velocity of the cell it started in.
+
+class _FrozenVelocity:
+    """vbar stand-in that always returns the velocity of the first cell it is asked for: the
+    planted mistake 'velocity frozen at the first cell' of a walk."""
+
+    def __init__(self, vb):
+        self.vb = vb
+        self.first = None
+
+    def __getitem__(self, c):
+        if self.first is None:
+            self.first = c
+        return self.vb[self.first]
+
+
+def _region_velocity(d, u_left, u_right):
+    """(u, 0) per cell: u_left where the cell's centroid has x < pi, u_right elsewhere."""
+    cx = d.mesh.P[..., 0].mean(axis=1) % (2 * np.pi)
+    u = np.where(cx < np.pi, u_left, u_right)
+    vb = np.zeros((d.mesh.ne, 2, d.nphi))
+    vb[:, 0, :] = u[:, None]
+    return vb
+
+
+def _region_feet(d, vb, u_left, u_right, tau, walk_vb=None):
+    """Walk feet and the hand-computed feet of the Gauss points of the triangles next to the
+    region boundary x = pi on the side the backward trace leaves."""
+    h = 2 * np.pi / int(round(np.sqrt(d.mesh.ne / 2)))
+    pts, _ = advect.sl_rule(d.p)
+    # the backward trace moves against the velocity
+    start_left = u_left < 0  # moving right: start left of pi, else right of pi
+    us, uo = (u_left, u_right) if start_left else (u_right, u_left)
+    got, want = [], []
+    for i in range(d.mesh.ne):
+        cx = d.mesh.P[i, :, 0].mean() % (2 * np.pi)
+        if start_left and not (np.pi - 1.5 * h < cx < np.pi):
+            continue
+        if not start_left and not (np.pi < cx < np.pi + 1.5 * h):
+            continue
+        for g in range(pts.shape[0]):
+            xg = d.mesh.P[i, 0] + d.Jmain[i] @ pts[g]
+            x0 = xg[0] % (2 * np.pi)
+            vbi = walk_vb() if walk_vb is not None else vb
+            c, (a, b), _ = advect.walk(d, vbi, i, pts[g], tau)
+            foot = d.mesh.P[c, 0] + d.Jmain[c] @ np.array([a, b])
+            s = -np.sign(us)  # direction of the backward trace
+            t_cross = abs(x0 - np.pi) / abs(us)
+            xf = x0 + s * abs(us) * tau if t_cross >= tau else np.pi + s * abs(uo) * (tau - t_cross)
+            got.append([foot[0] % (2 * np.pi), foot[1] % (2 * np.pi)])
+            want.append([xf, xg[1] % (2 * np.pi)])
+    return np.array(got), np.array(want)
+
+
+@pytest.mark.parametrize("u_left,u_right", [(0.4, 1.0), (-0.5, -1.3)])
+def test_walk_takes_each_cells_velocity(u_left, u_right):
+    """Unjittered periodic lattice, velocity (u, 0) constant in each cell, one value left of
+    x = pi and another right of it: the foot is x_g - u_start t_c - u_other (tau - t_c), with t_c
+    the time to reach x = pi, which a straight-line foot with one velocity misses."""
+    n, p = 8, 2
+    d = _disc(n, p, jitter=0.0)
+    h = 2 * np.pi / n
+    tau = 1.6 * h / max(abs(u_left), abs(u_right))
+    vb = _region_velocity(d, u_left, u_right)
+    got, want = _region_feet(d, vb, u_left, u_right, tau)
+    assert len(got) > 50
+    assert np.abs(got - want).max() <= 1e-12
+    # some points cross the region boundary, some do not
+    x0 = want[:, 0]
+    assert (np.abs(x0 - np.pi) > 1e-9).all()
+
+
+def test_planted_frozen_velocity_fails_the_region_pin():
+    """Planted mistake (on the CPU, in the oracle's input): every segment takes the velocity of
+    the cell the walk started in.  The region pin above must catch it."""
+    n, p = 8, 2
+    d = _disc(n, p, jitter=0.0)
+    h = 2 * np.pi / n
+    u_left, u_right = 0.4, 1.0
+    tau = 1.6 * h / u_right
+    vb = _region_velocity(d, u_left, u_right)
+    got, want = _region_feet(d, vb, u_left, u_right, tau, walk_vb=lambda: _FrozenVelocity(vb))
+    assert np.abs(got - want).max() > 1e-2
+
+
+def _e1_disc(n, p):
+    """Walled unit box, unjittered, with the velocity of the first numerical experiment of
+    Section 5 centred in the box, v = (-(x - 1/2), 0) (reading: v = (-x, 0), the only field
+    consistent with the printed exact solution C0(x e^t, y)).  The nodal interpolant of a
+    linear field is exact for p >= 1."""
+    d = _disc(n, p, periodic=False, jitter=0.0)
+    vb = advect.nodal_velocity(d, lambda q: np.stack([-(q[..., 0] - 0.5), 0.0 * q[..., 1]], -1))
+    return d, vb
+
+
+def _euler_per_cell_foot(n, xg, yg, tau):
+    """Foot of the per-cell Euler walk for v = (-(x - 1/2), 0) on the unjittered n x n split-square
+    lattice of the unit box, from the lattice lines alone: the horizontal backward trace from
+    (xg, yg), xg > 1/2, crosses the vertical lines x = a h and the diagonals x = a h + (yg - b h) of
+    its row b; inside a cell entered at x_s it moves as x_s + s (x_s - 1/2)."""
+    h = 1.0 / n
+    b = int(np.floor(yg / h))
+    lines = np.sort(np.concatenate([np.arange(n + 1) * h, np.arange(n) * h + (yg - b * h)]))
+    x, left = xg, tau
+    for c in lines[lines > xg + 1e-14]:
+        s = (c - x) / (x - 0.5)
+        if s >= left:
+            break
+        x, left = c, left - s
+    return x + left * (x - 0.5)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_walk_e1_velocity_matches_per_cell_euler(p):
+    """v = (-(x - 1/2), 0): every walk foot equals the per-cell Euler foot computed from the lattice
+    lines (exact to rounding), not the one-segment Euler foot x_g + tau (x_g - 1/2)."""
+    n = 8
+    d, vb = _e1_disc(n, p)
+    tau = 0.35
+    pts, _ = advect.sl_rule(p)
+    errs, frozen_gap, ncross = [], [], 0
+    for i in range(d.mesh.ne):
+        cx = d.mesh.P[i, :, 0].mean()
+        if not (0.55 < cx < 0.75):
+            continue
+        for g in range(pts.shape[0]):
+            xg = d.mesh.P[i, 0] + d.Jmain[i] @ pts[g]
+            c, (a, b), steps = advect.walk(d, vb, i, pts[g], tau)
+            foot = d.mesh.P[c, 0] + d.Jmain[c] @ np.array([a, b])
+            want = _euler_per_cell_foot(n, xg[0], xg[1], tau)
+            errs.append(max(abs(foot[0] - want), abs(foot[1] - xg[1])))
+            frozen_gap.append(abs(want - (xg[0] + tau * (xg[0] - 0.5))))
+            ncross += steps - 1
+    assert max(errs) <= 1e-12
+    assert ncross > 100 and max(frozen_gap) > 1e-3
+
+
+def test_walk_e1_converges_to_the_characteristic_at_first_order():
+    """v = (-(x - 1/2), 0): the exact foot is 1/2 + (x_g - 1/2) e^tau (the characteristic of the
+    first experiment of Section 5).  Straight segments per cell (explicit Euler, Section 3.5) are
+    first-order accurate: at fixed tau the foot error halves with h."""
+    tau = 0.6
+    errs = []
+    for n in (16, 32, 64, 128):
+        d, vb = _e1_disc(n, 1)
+        pts, _ = advect.sl_rule(1)
+        e = []
+        cx, cy = d.mesh.P[..., 0].mean(axis=1), d.mesh.P[..., 1].mean(axis=1)
+        for i in np.nonzero((cx > 0.6) & (cx < 0.7) & (np.abs(cy - 0.5) < 0.05))[0]:
+            for g in range(pts.shape[0]):
+                xg = d.mesh.P[i, 0] + d.Jmain[i] @ pts[g]
+                c, (a, b), _ = advect.walk(d, vb, i, pts[g], tau)
+                foot = d.mesh.P[c, 0] + d.Jmain[c] @ np.array([a, b])
+                e.append(foot[0] - (0.5 + (xg[0] - 0.5) * np.exp(tau)))
+        errs.append(np.sqrt(np.mean(np.square(e))))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 0.85) and np.all(orders < 1.2), (errs, orders)
+
+
+def test_sl_advect_e1_field_at_first_order():
+    """First experiment of Section 5 (v = (-(x - 1/2), 0), exact solution C0(1/2 + (x - 1/2) e^t, y)),
+    one step, p = 3, walls: the advected coefficients approach the nodal values of the exact
+    solution at first order in h (the Euler trajectories; the degree-3 projection error is far
+    smaller).  C0 is a smooth Gaussian: the printed e^{-100 r} is resolved only on meshes far larger
+    than a pure-Python walk covers in seconds.  Sampled triangles near the centre line."""
+    p, tau = 3, 0.6
+
+    def c0(x, y):
+        return np.exp(-3.0 * ((x - 0.5) ** 2 + (y - 0.5) ** 2))
+
+    errs = []
+    for n in (32, 64, 128):
+        d, vb = _e1_disc(n, p)
+        cx = d.mesh.P[..., 0].mean(axis=1)
+        cy = d.mesh.P[..., 1].mean(axis=1)
+        ids = np.nonzero((cx > 0.58) & (cx < 0.7) & (np.abs(cy - 0.5) < 0.12))[0]
+        ids = ids[:: max(1, len(ids) // 60)]
+        xy = d.main_node_xy()
+        q = c0(xy[..., 0], xy[..., 1])[:, None, :]
+        got = advect.sl_advect_rows(d, vb, q, tau, ids)[:, 0, :]
+        ex = c0(0.5 + (xy[ids, :, 0] - 0.5) * np.exp(tau), xy[ids, :, 1])
+        errs.append(np.sqrt(np.mean(np.square(got - ex))))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 0.85) and np.all(orders < 1.2), (errs, orders)

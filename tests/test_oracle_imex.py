@@ -286,3 +286,40 @@ def test_walls_rows_equal_assembled_rows():
     ids = np.arange(d.mesh.ne)
     got = imex.walls_rows(d, u, ids, side)
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def _ns_residual(vel, pres, xy, t, nu, h=1e-4):
+    """dv/dt + (v.grad) v + grad p - nu lap v at points xy, by central differences of the
+    closed-form fields (the incompressible momentum equation of Section 2 with g = 0)."""
+    ex, ey = np.array([h, 0.0]), np.array([0.0, h])
+    v = vel(xy, t, nu)
+    dvdt = (vel(xy, t + h, nu) - vel(xy, t - h, nu)) / (2 * h)
+    dvdx = (vel(xy + ex, t, nu) - vel(xy - ex, t, nu)) / (2 * h)
+    dvdy = (vel(xy + ey, t, nu) - vel(xy - ey, t, nu)) / (2 * h)
+    lap = (vel(xy + ex, t, nu) + vel(xy - ex, t, nu) + vel(xy + ey, t, nu) + vel(xy - ey, t, nu)
+           - 4 * v) / h ** 2
+    dpdx = (pres(xy + ex, t, nu) - pres(xy - ex, t, nu)) / (2 * h)
+    dpdy = (pres(xy + ey, t, nu) - pres(xy - ey, t, nu)) / (2 * h)
+    gradp = np.stack([dpdx, dpdy], axis=-1)
+    adv = v[..., :1] * dvdx + v[..., 1:] * dvdy
+    return dvdt + adv + gradp - nu * lap
+
+
+def test_tgv_fields_solve_the_momentum_equation():
+    """The Taylor-Green velocity and the oracle's pressure (Section 5, decay e^{-4 nu t}) satisfy
+    the momentum and continuity equations; the printed pressure decay e^{-2 nu t} does not."""
+    rng = np.random.default_rng(3)
+    xy = rng.uniform(0, 2 * np.pi, size=(200, 2))
+    for nu, t in [(1e-2, 0.7), (0.3, 1.9)]:
+        res = _ns_residual(imex.tgv_velocity, imex.tgv_pressure, xy, t, nu)
+        assert np.abs(res).max() <= 1e-6
+        h = 1e-5
+        div = ((imex.tgv_velocity(xy + [h, 0], t, nu) - imex.tgv_velocity(xy - [h, 0], t, nu))[:, 0]
+               + (imex.tgv_velocity(xy + [0, h], t, nu) - imex.tgv_velocity(xy - [0, h], t, nu))[:, 1]) / (2 * h)
+        assert np.abs(div).max() <= 1e-8
+
+    def printed(q, t, nu):
+        return 0.25 * (np.cos(2 * q[..., 0]) + np.cos(2 * q[..., 1])) * np.exp(-2.0 * nu * t)
+
+    res = _ns_residual(imex.tgv_velocity, printed, xy, 1.9, 0.3)
+    assert np.abs(res).max() > 1e-2
