@@ -46,7 +46,8 @@ typedef enum {
     SLD_E_MESH = 2,      /* invalid mesh: non-positive area, non-manifold edge, ... */
     SLD_E_NOMEM = 3,     /* device or host allocation failed */
     SLD_E_HIP = 4,       /* a HIP runtime call failed */
-    SLD_E_NOCONV = 5,    /* CG reached maxit; the best iterate and report are written */
+    SLD_E_NOCONV = 5,    /* CG stopped before rtol (maxit, or the FP64 rounding floor of the
+                            recomputed residual); the last iterate and report are written */
     SLD_E_BREAKDOWN = 6, /* CG breakdown: d.Ad <= 0 or a non-finite scalar */
     SLD_E_BUDGET = 7     /* a size or memory budget is exceeded */
 } sld_status;
@@ -172,8 +173,18 @@ sld_status sld_sl_advect(sld_disc disc, const double* vbar, const double* q, int
  *   (the kernel of K on a periodic or all-wall mesh) before the solve.
  *   p device [ne][N_phi]; in: initial guess if params->warm_start, out: the solution with
  *   int_Omega p dx = 0.
- * Stopping rule: ||r_k||_2 <= rtol ||b||_2 on coefficient vectors; the true residual is
- * recomputed at exit.  Iterations run as a captured HIP graph of graph_block iterations
+ * Stopping rule: ||b - K p||_2 <= rtol ||b||_2 on coefficient vectors, with the residual
+ * recomputed in FP64.  FP64: the iteration accumulates the correction to p since the last
+ * residual replacement; the recursive CG residual is replaced by the recomputed one (p absorbs
+ * the correction) whenever its norm has dropped by 1e-3 since the last replacement and whenever
+ * it meets its target (d and the CG scalars are kept, or the iteration restarts from the new
+ * residual when the two residuals differ by more than 30%).  When the recomputed residual
+ * misses rtol, the recursive target is lowered fourfold -- unless the difference between the
+ * two residuals, the rounding error of evaluating b - K p in FP64 (about
+ * eps || |K| |p| || / ||b||: 3e-12 on a 128x128x2, p = 3 mesh, 4e-11 on 512x512x2), is at least
+ * rtol / 2: rtol is then below what FP64 can confirm, and the solve returns SLD_E_NOCONV with
+ * converged = 0 and the recomputed residual in rel_res_true.
+ * Iterations run as a captured HIP graph of graph_block iterations
  * (scalars stay on the device); the calling thread blocks until the solve ends and reads the
  * scalars copied after each graph to test convergence.  From the second FP64 solve of a kind
  * (pressure or viscous) on a disc, the next graph is queued on `stream` before the current
@@ -203,13 +214,13 @@ typedef struct {
 
 typedef struct {
     int32_t iters;        /* CG iterations performed (mixed: inner iterations, summed) */
-    int32_t converged;    /* 1 if rtol was met */
-    double rel_res;       /* ||r|| / ||b|| at exit (FP64: recursive; mixed: FP64 residual) */
+    int32_t converged;    /* 1 if the recomputed residual met rtol */
+    double rel_res;       /* ||r|| / ||b|| at exit: the residual last recomputed in FP64 */
     double rel_res_true;  /* ||b - K p|| / ||b|| recomputed at exit */
     double seconds;       /* wall time of the solve on the host */
     double step_us;       /* profile only: mean time per CG iteration inside captured blocks */
     int32_t timed_iters;  /* profile only: iterations the mean is taken over */
-    int32_t outer_iters;  /* mixed only: reliable updates performed */
+    int32_t outer_iters;  /* FP64: residual replacements; mixed: reliable updates */
 } sld_cg_report;
 
 sld_status sld_cg_solve(sld_disc disc, const double* b, double* p, const sld_cg_params* params,

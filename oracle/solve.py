@@ -125,23 +125,26 @@ def gauge(disc: OracleDisc, p_main: np.ndarray) -> np.ndarray:
 
 
 def cg(K: sp.csr_matrix, b: np.ndarray, tol: float = 1e-12, maxit: int = 100000,
-       x0: np.ndarray | None = None, max_seconds: float | None = None):
+       x0: np.ndarray | None = None, max_seconds: float | None = None, matvec=None):
     """Plain conjugate gradients on A = -K for A x = -b (b projected onto 1^perp).
 
+    matvec: optional v -> K v (the same product by another library routine, e.g. a threaded
+    sparse kernel); default K @ v.
     Returns (x, info) with info = {iters, rel_res, rel_res_true, converged, seconds}.
     """
     t0 = time.perf_counter()
+    Kv = (lambda v: K @ v) if matvec is None else matvec
     shape = b.shape
     bb = -project_mean(b.reshape(-1))
     x = np.zeros_like(bb) if x0 is None else x0.reshape(-1).copy()
-    r = bb - (-(K @ x))
+    r = bb - (-Kv(x))
     d = r.copy()
     rr = float(r @ r)
     nb = float(np.sqrt(bb @ bb))
     it = 0
     converged = nb == 0.0 or np.sqrt(rr) <= tol * nb
     while not converged and it < maxit:
-        q = -(K @ d)
+        q = -Kv(d)
         alpha = rr / float(d @ q)
         x += alpha * d
         r -= alpha * q
@@ -156,7 +159,7 @@ def cg(K: sp.csr_matrix, b: np.ndarray, tol: float = 1e-12, maxit: int = 100000,
         d = r + beta * d
         if max_seconds is not None and time.perf_counter() - t0 > max_seconds:
             break
-    rt = bb - (-(K @ x))
+    rt = bb - (-Kv(x))
     info = {
         "iters": it,
         "rel_res": float(np.sqrt(rr) / nb) if nb > 0 else 0.0,

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -182,6 +183,7 @@ void free_disc(sld_disc_s* d) {
     if (!d) return;
     CgWork& w = d->cg;
     dfree(w.x);
+    dfree(w.e);
     for (int k = 0; k < 2; ++k) {
         dfree(w.r[k]);
         dfree(w.q[k]);
@@ -599,6 +601,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     if (e == hipSuccess) e = hipMalloc(&d->ops32_dev, h32.size());
     if (e == hipSuccess) e = hipMalloc(&d->sl_dev, hsl.size());
     if (e == hipSuccess) e = dalloc(&w.x, nv);
+    if (e == hipSuccess) e = dalloc(&w.e, nv);
     for (int k = 0; k < 2; ++k) {
         if (e == hipSuccess) e = dalloc(&w.r[k], nv);
         if (e == hipSuccess) e = dalloc(&w.q[k], nv);
@@ -879,6 +882,15 @@ hipError_t capture_block(sld_disc_s* d, bool fp32, bool shift, int gb, hipGraphE
     return e;
 }
 
+// SLD_CG_TRACE=1 in the environment: each FP64 residual replacement is printed to stderr
+bool cg_trace() {
+    static const bool on = [] {
+        const char* v = std::getenv("SLD_CG_TRACE");
+        return v != nullptr && v[0] == '1';
+    }();
+    return on;
+}
+
 struct IterStats {
     int iters = 0, done = 0, timed = 0;
     double t_step = 0;
@@ -1016,15 +1028,88 @@ sld_status cg_solve_impl(sld_disc d, const double* b, double* p, const sld_cg_pa
     typedef CgScalars S;
     SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, sigma, s));
     IterStats st;
-    int outer = 0, status = 0;  // status: 1 converged, 2 no convergence, 3 breakdown
+    // status: 1 converged, 2 no convergence (maxit, or the FP64 floor), 3 breakdown
+    int outer = 0, status = 0;
+    bool floor_stop = false;
     double rr = 0, bb = 0;
     if (!mixed) {
-        sld_status e = run_iterations(d, false, shift, prm->graph_block, prm->profile != 0, s,
-                                      w.scal, w.host_scal, &st);
-        if (e != SLD_OK) return e;
-        rr = w.host_scal[S::RR];
-        bb = w.host_scal[S::BB];
-        status = st.done;
+        // FP64 CG with residual replacement: the device stops when the recursive residual meets
+        // its target, or when it has dropped by kReplaceFactor since the last replacement; then
+        // x absorbs the accumulated correction, r = K x - b_int is recomputed in FP64 and the
+        // iteration resumes from it with d and q kept (restarted if the gap between the two
+        // residuals shows d is no longer conjugate to r).  The solve converges when the
+        // recomputed residual meets rtol.  If it misses after the recursive one met its target,
+        // the recursive target is lowered fourfold -- unless the gap itself is at least half of
+        // rtol: the evaluation of K x - b_int in FP64 is then too coarse to confirm rtol (the
+        // rounding floor, about eps | |K| |x| | / |b|), and the solve stops without convergence.
+        constexpr int kMaxTighten = 6;
+        int tighten = 0;
+        int base = 0;  // iterations of the segments before the last restart
+        // first iteration of the current segment: every captured block starts at parity 0, so
+        // the launch that ran iteration k read the buffers of parity (k - seg0) & 1
+        int seg0 = 0;
+        while (true) {
+            sld_status e = run_iterations(d, false, shift, prm->graph_block, prm->profile != 0, s,
+                                          w.scal, w.host_scal, &st);
+            if (e != SLD_OK) return e;
+            rr = w.host_scal[S::RR];
+            bb = w.host_scal[S::BB];
+            status = st.done;
+            const int seg_iters = (int)w.host_scal[S::ITER];
+            st.iters = base + st.iters;
+            if (status != S::kConverged && status != S::kRefresh) break;
+            if (w.host_scal[S::ZERO] != 0.0) {
+                status = S::kConverged;
+                break;
+            }
+            const int src = (seg_iters + 1 - seg0) & 1;
+            const double rr_rec = rr;
+            SLD_HIP_CHECK(launch_cg_replace(d, src, sigma, s));
+            SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
+                                         hipMemcpyDeviceToHost, s));
+            SLD_HIP_CHECK(hipStreamSynchronize(s));
+            ++outer;
+            const bool restarted = w.host_scal[S::ITER0] == 0.0;
+            const int total_iters = base + seg_iters;
+            if (restarted) {
+                base += seg_iters;
+                seg0 = 0;
+            } else {
+                seg0 = seg_iters + 1;
+            }
+            const double rr_true = w.host_scal[S::RR];
+            rr = rr_true;
+            if (cg_trace())
+                std::fprintf(stderr,
+                             "sld cg: replacement %d (%s) after iteration %d, src %d: recursive "
+                             "%.3e recomputed %.3e gap %.3e (relative to b)%s\n",
+                             outer, status == S::kConverged ? "rtol" : "refresh", total_iters, src,
+                             bb > 0 ? std::sqrt(rr_rec / bb) : 0.0,
+                             bb > 0 ? std::sqrt(rr_true / bb) : 0.0,
+                             bb > 0 ? std::sqrt(w.host_scal[S::GAP] / bb) : 0.0,
+                             restarted ? ", restart" : "");
+            if (!std::isfinite(rr_true)) {
+                status = S::kBreakdown;
+                break;
+            }
+            if (rr_true <= w.host_scal[S::TOLU]) {
+                status = S::kConverged;
+                break;
+            }
+            if (status == S::kConverged) {
+                if (w.host_scal[S::GAP] >= 0.25 * w.host_scal[S::TOLU] || ++tighten > kMaxTighten) {
+                    status = S::kMaxit;
+                    floor_stop = true;
+                    break;
+                }
+            }
+            if (st.iters >= prm->maxit) {
+                status = S::kMaxit;
+                break;
+            }
+        }
+        // the solution is x + e
+        SLD_HIP_CHECK(launch_cg_fold(d, s));
     } else {
         // FP32 CG with FP64 reliable updates.  The setup left r64 = K x - b_int (partials in
         // part_s); one Krylov process runs in FP32 and is refreshed in FP64 whenever its
@@ -1112,7 +1197,9 @@ sld_status cg_solve_impl(sld_disc d, const double* b, double* p, const sld_cg_pa
     if (status == 2) {
         sld_set_error(mixed ? "sld_cg_solve: refinement stopped before rtol (maxit, max_outer or "
                               "the FP64 residual floor)"
-                            : "sld_cg_solve: maxit reached before rtol");
+                    : floor_stop ? "sld_cg_solve: the recomputed residual stagnated above rtol (the "
+                                   "FP64 rounding floor of K x)"
+                                 : "sld_cg_solve: maxit reached before rtol");
         return SLD_E_NOCONV;
     }
     return SLD_OK;

@@ -71,9 +71,11 @@ __global__ __launch_bounds__(kBlockTri) void k_cg_resid(const RefOps<P>* __restr
                                                         double* __restrict__ part_out,
                                                         const double* __restrict__ scal,
                                                         double sigma,
-                                                        const unsigned char* __restrict__ wall_i) {
+                                                        const unsigned char* __restrict__ wall_i,
+                                                        int always) {
     constexpr int N = RefOps<P>::NPHI;
-    if (scal[S::DONE] != 0.0) return;
+    // (skipped when the setup found a zero right-hand side, unless asked for regardless)
+    if (!always && scal[S::DONE] != 0.0) return;
     __shared__ double sm[kTriPerBlock][4][N];
     const int tl = threadIdx.x / 3, al = threadIdx.x - 3 * (threadIdx.x / 3);
     double acc[1] = {0.0};
@@ -260,9 +262,10 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
         // every block takes the same decision from the same sums
         int stop = 0;
         if (!isfinite(rr)) stop = 3;
-        else if (rr <= scal[S::TOL2]) stop = 1;
-        else if (!(dq > 0.0) || !isfinite(dq)) stop = 3;
-        else if (it > scal[S::MAXIT]) stop = 2;
+        else if (rr <= scal[S::TOL2]) stop = S::kConverged;
+        else if (rr <= scal[S::RTH]) stop = S::kRefresh;
+        else if (!(dq > 0.0) || !isfinite(dq)) stop = S::kBreakdown;
+        else if (it > scal[S::MAXIT]) stop = S::kMaxit;
         if (stop) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 scal[S::DONE] = (double)stop;
@@ -527,12 +530,13 @@ __global__ __launch_bounds__(kBlockFlat) void k_scal_reduce(const double* __rest
 }
 
 // b_int = b - mean in internal order (gathered through perm); x = 0 (cold) or the gathered
-// initial guess (warm); d0 = q0 = 0; partials of |b_int|^2
+// initial guess (warm); e = d0 = q0 = 0; partials of |b_int|^2
 __global__ __launch_bounds__(kBlockFlat) void k_cg_prep(const double* __restrict__ b,
                                                         const double* __restrict__ p0,
                                                         const int* __restrict__ perm, int nphi,
                                                         int64_t n, double* __restrict__ bint,
                                                         double* __restrict__ x, int warm,
+                                                        double* __restrict__ e,
                                                         double* __restrict__ d0,
                                                         double* __restrict__ d1,
                                                         double* __restrict__ part,
@@ -546,6 +550,7 @@ __global__ __launch_bounds__(kBlockFlat) void k_cg_prep(const double* __restrict
         const double v = b[src] - mean;
         bint[t] = v;
         x[t] = warm ? p0[src] : 0.0;
+        e[t] = 0.0;
         d0[t] = 0.0;
         d1[t] = 0.0;
         acc[0] = fma(v, v, acc[0]);
@@ -570,6 +575,8 @@ __global__ __launch_bounds__(kBlockFlat) void k_cg_scal_init(const double* __res
         scal[S::ZERO] = bb == 0.0 ? 1.0 : 0.0;
         scal[S::DONE] = bb == 0.0 ? 1.0 : 0.0;
         scal[S::SIGMA] = sigma;
+        scal[S::RTH] = 0.0;
+        scal[S::TOLU] = rtol * rtol * bb;
     }
 }
 
@@ -677,6 +684,7 @@ __global__ __launch_bounds__(kBlockFlat) void k_rel_init(double* __restrict__ sc
         scal_in[S::RR] = 0.0;
         scal_in[S::TOL2] = rtol * rtol;  // relative: the scaled right-hand side has unit norm
         scal_in[S::MAXIT] = (double)maxit;
+        scal_in[S::RTH] = 0.0;  // the FP32 process is refreshed by the host's reliable updates
     }
 }
 
@@ -751,6 +759,84 @@ __global__ __launch_bounds__(kBlockFlat) void k_rel_peek(const double* __restric
     }
 }
 
+// ---------------------------------------------------------------- FP64 residual replacement
+// The FP64 iteration kernel accumulates x_k - x into e, so its rounding is relative to the
+// correction since the last replacement, not to x: x += e, e = 0 at each replacement.
+__global__ __launch_bounds__(kBlockFlat) void k_cg_fold(int64_t n, double* __restrict__ x,
+                                                        double* __restrict__ e) {
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        x[t] += e[t];
+        e[t] = 0.0;
+    }
+}
+
+// The state the iteration kernel stopped on lives in the buffers of parity src; rt holds the
+// recomputed residual K x - b_int (written into the free buffers of parity 1 - src).  r, d and q
+// of the replaced state go to buffers 0 (the first launch of every captured block reads buffers
+// 0), the partials of rr = r.r, dq = d.q, rq = r.q, qq = q.q of this state to the partial slot
+// the first launch reads, and those of |rt - r_recursive|^2 to gap_part.
+// (rs and r0 are the same buffer when src = 0: no __restrict__ here)
+__global__ __launch_bounds__(kBlockFlat) void k_rep_state(int64_t n, const double* rt,
+                                                          const double* rs, const double* qs,
+                                                          const double* ds, double* r0, double* q0,
+                                                          double* d0, int src,
+                                                          double* __restrict__ part,
+                                                          double* __restrict__ gap_part) {
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        const double r = rt[t], q = qs[t], dd = ds[t], g = r - rs[t];
+        if (src == 0) {
+            r0[t] = r;  // rt is buffer 1: move r; q and d are in place
+        } else {
+            q0[t] = q;  // rt is buffer 0 already: move q and d
+            d0[t] = dd;
+        }
+        acc[0] = fma(r, r, acc[0]);
+        acc[1] = fma(dd, q, acc[1]);
+        acc[2] = fma(r, q, acc[2]);
+        acc[3] = fma(q, q, acc[3]);
+        acc[4] = fma(g, g, acc[4]);
+    }
+    block_sum_all<5, kBlockFlat>(acc);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) part[c * gridDim.x + blockIdx.x] = acc[c];
+        gap_part[blockIdx.x] = acc[4];
+    }
+}
+
+// one block: RR and GAP from the partials; resume the iteration from the replaced state, or
+// restart it from the new residual when the gap shows the kept direction is no longer conjugate
+__global__ __launch_bounds__(kBlockFlat) void k_rep_scal(const double* __restrict__ part,
+                                                         const double* __restrict__ gap_part,
+                                                         int nb, double* __restrict__ scal,
+                                                         double factor2, double gapmax2) {
+    const double rr = reduce_partials<kBlockFlat>(part, nb);
+    const double gap = reduce_partials<kBlockFlat>(gap_part, nb);
+    if (threadIdx.x == 0) {
+        const double done_iters = scal[S::ITER];
+        // stopped at rtol on the recursive residual, but the recomputed one misses the target:
+        // aim the recursive residual lower
+        if (scal[S::DONE] == (double)S::kConverged && rr > scal[S::TOLU])
+            scal[S::TOL2] = 0.25 * scal[S::TOL2];
+        scal[S::RR] = rr;
+        scal[S::GAP] = gap;
+        scal[S::RTH] = factor2 * rr;
+        scal[S::DONE] = 0.0;
+        if (gap > gapmax2 * rr) {
+            // the next launch is a first launch: alpha = beta = 0, d = r
+            scal[S::ITER0] = 0.0;
+            scal[S::ITER1] = 0.0;
+            scal[S::MAXIT] = scal[S::MAXIT] - done_iters;
+        } else {
+            scal[S::ITER0] = done_iters + 1.0;  // the launch that stopped, run again
+            scal[S::ITER1] = done_iters;
+        }
+    }
+}
+
 template <int P>
 const RefOps<P>* ops_of(const sld_disc_s* d) { return reinterpret_cast<const RefOps<P>*>(d->ops_dev); }
 template <int P>
@@ -780,13 +866,41 @@ hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p
     hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal,
                        (int)S::MEAN, sigma > 0.0 ? 0.0 : 1.0 / (double)n);
     hipLaunchKernelGGL(k_cg_prep, dim3(G), dim3(kBlockFlat), 0, s, b, p0, m->perm, d->nphi, n, w.b,
-                       w.x, warm ? 1 : 0, w.d[0], w.q[0], w.part_s, w.scal);
+                       w.x, warm ? 1 : 0, w.e, w.d[0], w.q[0], w.part_s, w.scal);
     hipLaunchKernelGGL(k_cg_scal_init, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal, rtol,
                        maxit, sigma);
     // r_0 = K x - b_int (the residual of -K x = -b_int); q, d of "iteration -1" are zero
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(G), dim3(kBlockTri), 0, s,
                                           ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
-                                          w.r[0], w.part_s, w.scal, sigma, w.wall_i));
+                                          w.r[0], w.part_s, w.scal, sigma, w.wall_i, 0));
+    // first residual replacement once |r| has dropped by kReplaceFactor from |r_0|
+    hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, G, w.scal,
+                       (int)S::RTH, kReplaceFactor * kReplaceFactor);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_fold(const sld_disc_s* d, hipStream_t s) {
+    const CgWork& w = d->cg;
+    hipLaunchKernelGGL(k_cg_fold, dim3(w.grid), dim3(kBlockFlat), 0, s, d->mesh->ne * d->nphi, w.x,
+                       w.e);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_replace(const sld_disc_s* d, int src, double sigma, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    const CgWork& w = d->cg;
+    const int G = w.grid;
+    const int64_t n = m->ne * d->nphi;
+    if (src != 0 && src != 1) return hipErrorInvalidValue;
+    const int fr = 1 - src;  // the buffers of the state before: free
+    hipLaunchKernelGGL(k_cg_fold, dim3(G), dim3(kBlockFlat), 0, s, n, w.x, w.e);
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(G), dim3(kBlockTri), 0, s,
+                                          ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
+                                          w.r[fr], w.part_s, w.scal, sigma, w.wall_i, 1));
+    hipLaunchKernelGGL(k_rep_state, dim3(G), dim3(kBlockFlat), 0, s, n, w.r[fr], w.r[src],
+                       w.q[src], w.d[src], w.r[0], w.q[0], w.d[0], src, w.part, w.part_s);
+    hipLaunchKernelGGL(k_rep_scal, dim3(1), dim3(kBlockFlat), 0, s, w.part, w.part_s, G, w.scal,
+                       kReplaceFactor * kReplaceFactor, kGapRestart * kGapRestart);
     return hipGetLastError();
 }
 
@@ -812,7 +926,7 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F, SH, ST>), dim3(G), \
                                           dim3(F ? kBlockCG : kBlockTri), lds, s, ops_of<PP>(d), \
                                           m->geo_i, m->geo_nb,                                  \
-                                          m->nbr_i, m->halo_pad, m->hmax, m->ne, w.wall_i, w.x, \
+                                          m->nbr_i, m->halo_pad, m->hmax, m->ne, w.wall_i, w.e, \
                                           w.r[parity], w.q[parity], w.d[parity], w.r[o],        \
                                           w.q[o], w.d[o], w.part + parity * 4 * G,              \
                                           w.part + o * 4 * G, w.scal, parity))
@@ -949,7 +1063,7 @@ hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s) {
     hipLaunchKernelGGL(k_rel_accumulate, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.x, w.e32, w.scal);
     SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(w.grid), dim3(kBlockTri), 0, s,
                                           ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b,
-                                          w.r[0], w.part_s, w.scal, 0.0, w.wall_i));
+                                          w.r[0], w.part_s, w.scal, 0.0, w.wall_i, 0));
     hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal,
                        (int)S::RR, 1.0);
     hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],

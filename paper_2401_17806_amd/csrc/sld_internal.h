@@ -65,6 +65,8 @@ struct sld_mesh_s {
 constexpr int kCgMaxGrid = 4096;     // blocks of the three-lane CG kernel (grid-stride beyond)
 struct CgWork {
     double* x = nullptr;
+    double* e = nullptr;           // FP64 CG: the correction to x since the last residual
+                                   // replacement (the iteration kernel accumulates into e)
     double* r[2] = {nullptr, nullptr};  // ping-pong by iteration parity
     double* q[2] = {nullptr, nullptr};
     double* d[2] = {nullptr, nullptr};
@@ -126,8 +128,14 @@ struct CgScalars {
     // layout of CgWork::scal (doubles)
     enum { RR = 0, BB = 1, TOL2 = 2, ITER = 3, DONE = 4, MAXIT = 5, MEAN = 6, ZERO = 7,
            RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, IRS = 12, RRNOW = 13, GAP = 14, SIGMA = 15,
-           NSCAL = 16 };
+           RTH = 16, TOLU = 17, NSCAL = 18 };
+    // DONE codes written by the iteration kernel
+    enum { kConverged = 1, kMaxit = 2, kBreakdown = 3, kRefresh = 4 };
 };
+// FP64 CG: the recursive residual is replaced by the recomputed one whenever its norm has dropped
+// by this factor since the last replacement (and whenever it meets rtol)
+constexpr double kReplaceFactor = 1e-3;
+constexpr double kGapRestart = 0.3;
 int cg_grid_for(const sld_disc_s* d, bool* front);
 // sigma > 0: the viscous system (sigma Mbar - K) x = -b instead of -K x = -b (no 1^perp
 // projection, no gauge)
@@ -135,6 +143,17 @@ hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p
                            double rtol, int maxit, double sigma, hipStream_t s);
 hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream_t s);
 hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hipStream_t s);
+// FP64 residual replacement on the state the iteration kernel stopped on (buffers of parity src):
+// x += e, e = 0; r = K x - b_int recomputed in FP64, d and q kept (moved to buffers 0), the four
+// dots summed directly; scal: RR = |r|^2, GAP = |r - r_recursive|^2, DONE cleared,
+// RTH = kReplaceFactor^2 RR; after a stop at rtol whose recomputed residual misses the target
+// TOLU, the recursive target TOL2 is lowered fourfold; ITER0 = ITER + 1 -- or, when
+// GAP > kGapRestart^2 RR (the kept
+// direction is no longer conjugate to the new residual), a restart: ITER0 = 0 (the next launch
+// takes d = r) and MAXIT reduced by the iterations done
+hipError_t launch_cg_replace(const sld_disc_s* d, int src, double sigma, hipStream_t s);
+// x += e, e = 0 (FP64 CG, before the solution is read)
+hipError_t launch_cg_fold(const sld_disc_s* d, hipStream_t s);
 // Dirichlet wall flags of the next diffusion solve from a per-edge mask (device [nd], NULL none)
 hipError_t launch_wall_mask(const sld_disc_s* d, const unsigned char* edge_mask, hipStream_t s);
 hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s);

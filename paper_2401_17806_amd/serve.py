@@ -4,9 +4,10 @@ meshes of different sizes and degrees, run through the library's continuous-batc
 
 Each request is (mesh n, degree p, precision, seed): the pressure stage right-hand side
 b = D v* of a seeded Gaussian random Fourier velocity field v* (|k| <= kmax, amplitude ~ |k|^-2)
-sampled at the dual nodes, solved to rtol (FP64: recursive residual 1e-12, as the oracle's
-CG; mixed: true FP64 residual 1e-10, below the true residual FP64 CG attains on the larger
-meshes).  Every request brings its own jittered mesh (seed =
+sampled at the dual nodes, solved to a recomputed FP64 relative residual of 1e-10 in both
+precisions (the FP64 rounding floor of K x - b is about 1e-11 on the largest meshes of the
+mix, so tighter tolerances cannot be confirmed there).  Every request brings its own jittered
+mesh (seed =
 request seed).  On arrival it is set up on the device (mesh tables, discretisation, right-hand
 side) as soon as the device-memory budget allows, submitted to the server, and freed when its
 result is in.  Latency = arrival -> result ready on the host, setup included.
@@ -85,7 +86,7 @@ def _tgv_dual(disc, torch):
     return torch.from_numpy(np.ascontiguousarray(u)).to(f"cuda:{disc.mesh.device}")
 
 
-def run(requests, arrivals, *, workers=4, budget_bytes=32 << 30, rtol=1e-12,
+def run(requests, arrivals, *, workers=4, budget_bytes=32 << 30, rtol=1e-10,
         mixed_rtol=1e-10, kmax=8, graph_block=32, poll_sleep=50e-6, keep_solutions=False,
         progress=0):
     """Submit each request at its arrival time (seconds after start); returns per-request

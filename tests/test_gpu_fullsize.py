@@ -4,8 +4,9 @@ systems quickly, so outputs are checked on samples it computes one by one:
   * the Schur apply on 256 sampled triangles (rows of eq. pressure_final, oracle.schur_rows);
   * the 128x128x2, p = 3 pressure against the oracle's own solve at 512 sampled DOFs
     (tests/golden/c2_pressure_sample.txt, written by make_c2_sample.py from the oracle);
-  * on the 512x512x2 mesh, properties that hold at any size: the true residual on sampled
-    rows and the zero-mean gauge; the mixed form's pressure against the FP64 one.
+  * the 512x512x2, p = 3 pressure, FP64 and mixed, against the oracle's solve at 1024 sampled
+    DOFs (tests/golden/c3_pressure_sample.txt, written by make_c3_sample.py from the oracle),
+    and the report of a tolerance below the FP64 rounding floor of the recomputed residual.
 """
 import math
 import os
@@ -78,9 +79,12 @@ def test_fullsize_schur_apply_sampled_rows(torch_dev, n, p, seed, walls):
     assert rel <= 1e-12
 
 
-def _read_sample():
+def _read_sample(name):
+    path = os.path.join(HERE, "golden", name)
+    if not os.path.exists(path):
+        pytest.fail(f"missing oracle sample {path} (tests/golden/make_*.py writes it)")
     idx, val, head = [], [], {}
-    for line in open(os.path.join(HERE, "golden", "c2_pressure_sample.txt")):
+    for line in open(path):
         if line.startswith("#"):
             parts = line[1:].split()
             for k in range(0, len(parts) - 1):
@@ -93,65 +97,83 @@ def _read_sample():
     return np.array(idx), np.array(val), head
 
 
+def _sample_err(p, sample):
+    idx, val, head = sample
+    got = p.cpu().numpy().ravel()[idx]
+    return np.abs(got - val).max() / head["maxabs_p"]
+
+
 def test_fullsize_c2_pressure_matches_oracle_sample(torch_dev):
-    """Bench workload (128x128x2, p = 3, FP64, rtol 1e-12, graph blocks of 64): the pressure
-    at 512 sampled DOFs equals the oracle's to 1e-9 of its max norm."""
+    """128x128x2, p = 3, FP64 to a recomputed residual of 1e-11 (the FP64 rounding floor of
+    K x - b is about 3e-12 here), graph blocks of 256: converged, and the pressure at 512 sampled
+    DOFs equals the oracle's to 1e-9 of its max norm."""
     torch = torch_dev
     _say("[fullsize c2 solve]")
     od, mesh, disc = _setup(128, 3, 2)
     b = _rhs(torch, od, disc, 128, 102)
-    p_gpu, rep = disc.sld_cg_solve(b, rtol=1e-12, graph_block=64, maxit=100000)
+    p_gpu, rep = disc.sld_cg_solve(b, rtol=1e-11, graph_block=256, maxit=100000)
     _say("   report", rep)
-    idx, val, head = _read_sample()
-    got = p_gpu.cpu().numpy().ravel()[idx]
-    err = np.abs(got - val).max() / head["maxabs_p"]
+    err = _sample_err(p_gpu, _read_sample("c2_pressure_sample.txt"))
     _say(f"    sampled max error / max|p| = {err:.2e}")
-    assert rep["converged"]
+    assert rep["status"] == "SLD_OK" and rep["converged"] and rep["rel_res_true"] <= 1e-11
     assert err <= 1e-9
 
 
-def test_fullsize_c3_solution_properties(torch_dev):
-    """512x512x2, p = 3: FP64 solve in the bench configuration; the true residual on 256
-    sampled rows is at the FP64 floor, the gauge holds, and the mixed form's pressure agrees
-    with the FP64 one."""
+def test_fullsize_c3_fp64_and_mixed_match_oracle_sample(torch_dev):
+    """512x512x2, p = 3 (the bench workload): FP64 and mixed precision, each to a recomputed
+    residual of 1e-10, converge, and each pressure equals the oracle's at 1024 sampled DOFs
+    (tests/golden/c3_pressure_sample.txt) to 1e-9 of its max norm; the gauge holds."""
     torch = torch_dev
-    _say("[fullsize c3 solve]")
+    _say("[fullsize c3 solves]")
     od, mesh, disc = _setup(512, 3, 3)
     b = _rhs(torch, od, disc, 512, 103)
-    p64, rep = disc.sld_cg_solve(b, rtol=1e-12, graph_block=64, maxit=200000)
-    _say("   fp64 report", rep)
-    assert rep["converged"]
-    bh = b.cpu().numpy()
-    bh = bh - bh.mean()
-    ph = p64.cpu().numpy()
-    ids = np.sort(np.random.default_rng(5).choice(mesh.ne, 256, replace=False))
-    res = bh[ids] - solve.schur_rows(od, ph, ids)
-    rel = np.linalg.norm(res) / np.linalg.norm(bh[ids])
-    _say(f"    sampled true residual {rel:.2e} (reported full {rep['rel_res_true']:.2e})")
-    assert rel <= 1e-7
+    sample = _read_sample("c3_pressure_sample.txt")
     w = od.main_weights()
-    assert abs((w * ph).sum()) <= 1e-12 * np.abs(ph).max() * w.sum()
-    pm, repm = disc.sld_cg_solve(b, rtol=1e-11, precision="mixed", graph_block=64, maxit=200000)
-    _say("   mixed report", repm)
-    d = np.linalg.norm(pm.cpu().numpy() - ph) / np.linalg.norm(ph)
-    _say(f"    mixed vs fp64 rel L2 {d:.2e}")
-    assert repm["rel_res_true"] <= 1e-10
-    assert d <= 1e-9
+    for prec in ("fp64", "mixed"):
+        p, rep = disc.sld_cg_solve(b, rtol=1e-10, precision=prec, graph_block=256 if prec == "fp64"
+                                   else 64, maxit=200000)
+        err = _sample_err(p, sample)
+        _say(f"   {prec} report {rep}; sampled max error / max|p| = {err:.2e}")
+        assert rep["status"] == "SLD_OK" and rep["converged"] and rep["rel_res_true"] <= 1e-10
+        assert err <= 1e-9
+        ph = p.cpu().numpy()
+        assert abs((w * ph).sum()) <= 1e-12 * np.abs(ph).max() * w.sum()
+
+
+def test_fullsize_c3_below_the_fp64_floor_is_reported(torch_dev):
+    """512x512x2, p = 3, rtol 1e-11: the FP64 rounding error of the recomputed residual K x - b
+    itself is about 4e-11 of |b| here, so neither form can confirm 1e-11.  Both stop at that
+    floor with SLD_E_NOCONV and converged false, the report names the floor, and the iterate
+    still equals the oracle's at the sampled DOFs to 1e-9."""
+    torch = torch_dev
+    _say("[fullsize c3 floor]")
+    od, mesh, disc = _setup(512, 3, 3)
+    b = _rhs(torch, od, disc, 512, 103)
+    sample = _read_sample("c3_pressure_sample.txt")
+    for prec in ("fp64", "mixed"):
+        p, rep = disc.sld_cg_solve(b, rtol=1e-11, precision=prec, graph_block=256 if prec == "fp64"
+                                   else 64, maxit=200000)
+        err = _sample_err(p, sample)
+        _say(f"   {prec} report {rep}; sampled max error / max|p| = {err:.2e}")
+        assert rep["status"] == "SLD_E_NOCONV" and not rep["converged"]
+        assert 1e-11 < rep["rel_res_true"] <= 1e-10
+        assert err <= 1e-9
 
 
 def test_fullsize_cavity_solve_properties(torch_dev):
-    """256x256x2 walled unit box, p = 2 (the cavity mesh), FP64 solve in the bench
-    configuration: converged, true residual on sampled rows (wall triangles included) at the
-    FP64 floor, zero-mean gauge."""
+    """256x256x2 walled unit box, p = 2 (the cavity mesh), FP64 solve to a recomputed residual of
+    1e-11 (the FP64 rounding floor of K x - b is about 2e-12 here): converged, the residual on
+    sampled rows (wall triangles included) computed by the oracle row by row, zero-mean
+    gauge."""
     torch = torch_dev
     _say("[fullsize cavity solve]")
     od, mesh, disc = _setup(256, 2, 4, walls=True)
     coef = A_SS * 0.5 * (1.0 / 256)
     vs = random_fourier_field(104, kmax=8, length=1.0)(od.dual_node_xy()).transpose(0, 2, 1)
     b = disc.sld_pressure_rhs(torch.from_numpy(np.ascontiguousarray(vs)).to("cuda:0"), 1.0 / coef)
-    p64, rep = disc.sld_cg_solve(b, rtol=1e-12, graph_block=64, maxit=200000)
+    p64, rep = disc.sld_cg_solve(b, rtol=1e-11, graph_block=64, maxit=200000)
     _say("   report", rep)
-    assert rep["converged"]
+    assert rep["status"] == "SLD_OK" and rep["converged"] and rep["rel_res_true"] <= 1e-11
     bh = b.cpu().numpy()
     bh = bh - bh.mean()
     ph = p64.cpu().numpy()
@@ -160,7 +182,7 @@ def test_fullsize_cavity_solve_properties(torch_dev):
     res = bh[ids] - solve.schur_rows(od, ph, ids)
     rel = np.linalg.norm(res) / np.linalg.norm(bh[ids])
     _say(f"    sampled true residual {rel:.2e}")
-    assert rel <= 1e-7
+    assert rel <= 1e-9
     w = od.main_weights()
     assert abs((w * ph).sum()) <= 1e-12 * np.abs(ph).max() * w.sum()
 

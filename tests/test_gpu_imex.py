@@ -152,8 +152,9 @@ def test_imex_tgv128_p3_fifty_steps_properties(torch_dev):
     dt = 0.5 * 2 * np.pi / n
     e0 = e_prev = float((vg * vg).sum())
     for k in range(steps):
-        rep = st.sld_imex_step(vg, pg, dt, nu, rtol=1e-12, visc_rtol=1e-12)
-        assert rep["pressure"]["converged"]
+        # (the recomputed pressure residual's FP64 floor on this mesh is about 3e-12)
+        rep = st.sld_imex_step(vg, pg, dt, nu, rtol=1e-11, visc_rtol=1e-12)
+        assert rep["pressure"]["converged"] and rep["status"] == "SLD_OK"
         dv = float(torch.linalg.norm(disc.sld_divergence(vg)))
         e = float((vg * vg).sum())
         if k % 10 == 0 or k == steps - 1:

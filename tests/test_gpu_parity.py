@@ -298,7 +298,8 @@ def test_chunked_cg_variant_parity(torch_dev, monkeypatch, n, p, periodic, strea
     f = random_fourier_field(19, kmax=4, length=(2 * np.pi if periodic else 1.0))
     b = solve.divergence(od, f(od.dual_node_xy()).transpose(0, 2, 1))
     x_or = solve.gauge(od, solve.cg(K, b, tol=1e-13)[0])
-    p64, rep = disc.sld_cg_solve(_to(torch, b), rtol=1e-13, maxit=20000, graph_block=8)
+    # (1e-12: the FP64 rounding floor of the recomputed residual is near 1e-13 on these meshes)
+    p64, rep = disc.sld_cg_solve(_to(torch, b), rtol=1e-12, maxit=20000, graph_block=8)
     pm, repm = disc.sld_cg_solve(_to(torch, b), rtol=1e-11, precision="mixed", maxit=20000,
                                  graph_block=8)
     fv = random_vector((od.mesh.ne, 1, od.nphi), seed=29)
@@ -307,5 +308,5 @@ def test_chunked_cg_variant_parity(torch_dev, monkeypatch, n, p, periodic, strea
     r64, rm = _rel(p64.cpu().numpy(), x_or), _rel(pm.cpu().numpy(), x_or)
     rv = _rel(xv.cpu().numpy(), want_v)
     _say(f"    fp64 {r64:.2e} ({rep['iters']} it)  mixed {rm:.2e}  viscous {rv:.2e}")
-    assert rep["converged"] and repm["status"] == "SLD_OK" and repv["converged"]
+    assert rep["status"] == "SLD_OK" and repm["status"] == "SLD_OK" and repv["converged"]
     assert r64 <= SOLVE_TOL and rm <= SOLVE_TOL and rv <= 1e-10

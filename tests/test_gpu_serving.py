@@ -110,7 +110,7 @@ def test_serving_loop_poisson_small(torch_dev):
             mesh = sld.Mesh(*q["mesh"], device=0)
             disc = sld.Disc(mesh, q["p"])
             b = serve._rhs(disc, q["seed"], 4, torch)
-            tol = 1e-10 if q["precision"] == "mixed" else 1e-12
+            tol = 1e-10
             x, rep = disc.sld_cg_solve(b, rtol=tol, precision=q["precision"], graph_block=32,
                                        maxit=200000)
             assert rep["iters"] == rec["iters"]
@@ -202,7 +202,7 @@ def test_serving_loop_with_imex_requests(torch_dev):
             st = sld.State(disc)
             v = serve._tgv_dual(disc, torch)
             p = torch.zeros(disc.main_shape, dtype=torch.float64, device="cuda:0")
-            tol = 1e-10 if q["precision"] == "mixed" else 1e-12
+            tol = 1e-10
             rep = st.sld_imex_step(v, p, 0.5 * 2 * np.pi / q["n"], 1e-2, rtol=tol,
                                    precision=q["precision"], graph_block=32, maxit=200000,
                                    warm_start=False)
