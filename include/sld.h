@@ -226,6 +226,24 @@ typedef struct {
 sld_status sld_cg_solve(sld_disc disc, const double* b, double* p, const sld_cg_params* params,
                         sld_cg_report* report, void* stream);
 
+/* sld_cg_solve_static: sld_cg_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same FP64
+ * iteration, residual replacement and stopping rule, with the CG workspace (vectors, dot
+ * partials, scalars) in a static device array of the library instead of the disc's workspace,
+ * and plain kernel launches instead of captured graphs (a synchronisation after every
+ * graph_block iterations); it calls no hipMalloc, hipFree or other allocating routine.
+ *   Limit: the array holds 2^23 doubles (64 MiB) per device, enough for about 9.3e5 DOFs
+ *   (ne * N_phi: e.g. a 215x215x2 mesh at p = 3); a larger disc returns SLD_E_BUDGET.  The
+ *   array is set aside on each device the library runs on until the process ends.
+ *   params: precision must be 0 (FP64) and profile 0 (SLD_E_INVALID otherwise).
+ *   Every call on a device shares that device's array and the disc's pinned scalar mirror:
+ *   calls that overlap on one device race (results undefined); calls in turn are independent
+ *   (each call's setup rewrites every workspace word it reads).
+ * Blocks like sld_cg_solve; results equal sld_cg_solve's up to rounding (the same kernels in
+ * the same order). */
+sld_status sld_cg_solve_static(sld_disc disc, const double* b, double* p,
+                               const sld_cg_params* params, sld_cg_report* report, void* stream);
+
 /* ------------------------------------------------------------------ IMEX time step (Section 4)
  * Grid transfers (eqs. d2m and m2d), the L2 projections between the main and the dual space
  * through the operator U of eq. u (U_ij[k][l] = int over T_ij of psi_k^(j) phi_l^(i)):

@@ -999,11 +999,48 @@ sld_status run_block(sld_disc_s* d, int gb, hipStream_t s, IterStats* st) {
     return SLD_OK;
 }
 
+// The FP64 iterations without graphs: blocks of gb plain launches, each followed by a copy of
+// the scalars into slot 1 of the pinned mirror and a stream synchronisation (no graph
+// instantiation and no event creation: nothing is allocated).
+sld_status run_plain(const sld_disc_s* d, int gb, hipStream_t s, double* scal, double* hs,
+                     IterStats* st) {
+    typedef CgScalars S;
+    double* slot = hs + S::NSCAL;
+    while (true) {
+        for (int k = 0; k < gb; ++k) SLD_HIP_CHECK(launch_cg_step(d, k & 1, false, s));
+        SLD_HIP_CHECK(hipMemcpyAsync(slot, scal, S::NSCAL * sizeof(double), hipMemcpyDeviceToHost, s));
+        SLD_HIP_CHECK(hipStreamSynchronize(s));
+        st->done = (int)slot[S::DONE];
+        const int launched = (int)std::max(slot[S::ITER0], slot[S::ITER1]);
+        st->iters = st->done ? (int)slot[S::ITER] : launched - 1;
+        if (st->done) {
+            std::memcpy(hs, slot, S::NSCAL * sizeof(double));
+            return SLD_OK;
+        }
+    }
+}
+
 // CG driver.  sigma = 0: the pressure system K p = b; sigma > 0: the viscous system
-// (sigma Mbar - K) p = -b (FP64 only).
-sld_status cg_solve_impl(sld_disc d, const double* b, double* p, const sld_cg_params* prm,
-                         sld_cg_report* rep, void* stream, double sigma) {
-    SLD_REQUIRE(d && b && p && prm, SLD_E_INVALID, "sld_cg_solve: NULL argument");
+// (sigma Mbar - K) p = -b (FP64 only).  ws != nullptr: FP64 pressure solve with the CG
+// workspace (vectors, partials, scalars) in ws instead of the disc's, run by plain launches.
+sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg_params* prm,
+                         sld_cg_report* rep, void* stream, double sigma, double* ws = nullptr);
+
+size_t static_words(int64_t n) { return (size_t)((n + 31) & ~int64_t(31)); }
+
+// Doubles of the static CG workspace for n DOFs and a grid of G blocks: x, e, b, r, q, d (two
+// of each of the last three), partials, scalars; every array starts on a 256-byte boundary.
+size_t static_ws_doubles(int64_t n, int G) {
+    return 9 * static_words(n) + static_words(10 * (int64_t)G) + static_words(CgScalars::NSCAL);
+}
+
+}  // namespace
+
+// CG driver (see the declaration above)
+namespace {
+sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg_params* prm,
+                         sld_cg_report* rep, void* stream, double sigma, double* ws) {
+    SLD_REQUIRE(d_in && b && p && prm, SLD_E_INVALID, "sld_cg_solve: NULL argument");
     SLD_REQUIRE(prm->rtol > 0 && std::isfinite(prm->rtol), SLD_E_INVALID,
                 "sld_cg_solve: rtol must be positive");
     SLD_REQUIRE(prm->maxit >= 1, SLD_E_INVALID, "sld_cg_solve: maxit must be >= 1");
@@ -1020,12 +1057,49 @@ sld_status cg_solve_impl(sld_disc d, const double* b, double* p, const sld_cg_pa
         SLD_REQUIRE(prm->max_outer >= 1, SLD_E_INVALID, "sld_cg_solve: max_outer must be >= 1");
         SLD_REQUIRE(prm->profile == 0, SLD_E_INVALID, "sld_cg_solve: profile is FP64-only");
     }
-    SLD_REQUIRE_DEVICE(d, "sld_cg_solve");
-    DeviceGuard dg(d->mesh->device);
+    SLD_REQUIRE_DEVICE(d_in, "sld_cg_solve");
+    DeviceGuard dg(d_in->mesh->device);
     hipStream_t s = (hipStream_t)stream;
     const auto t0 = std::chrono::steady_clock::now();
-    CgWork& w = d->cg;
     typedef CgScalars S;
+    // the static-workspace solve runs on a shallow copy of the disc whose CG workspace points
+    // into ws (the pinned scalar mirror stays the disc's)
+    sld_disc_s shadow;
+    sld_disc_s* d = d_in;
+    if (ws != nullptr) {
+        SLD_REQUIRE(!mixed && !shift && prm->profile == 0, SLD_E_INVALID,
+                    "sld_cg_solve_static: FP64 pressure solves only, without profile");
+        shadow.mesh = d_in->mesh;
+        shadow.p = d_in->p;
+        shadow.nphi = d_in->nphi;
+        shadow.npsi = d_in->npsi;
+        shadow.ops_dev = d_in->ops_dev;
+        shadow.ops_bytes = d_in->ops_bytes;
+        CgWork& sw = shadow.cg;
+        const CgWork& dw = d_in->cg;
+        const int64_t n = d_in->mesh->ne * d_in->nphi;
+        const size_t nw = static_words(n);
+        double* q = ws;
+        sw.x = q; q += nw;
+        sw.e = q; q += nw;
+        sw.b = q; q += nw;
+        for (int k = 0; k < 2; ++k) {
+            sw.r[k] = q; q += nw;
+            sw.q[k] = q; q += nw;
+            sw.d[k] = q; q += nw;
+        }
+        sw.part = q;
+        sw.part_s = q + 8 * (int64_t)dw.grid;
+        q += static_words(10 * (int64_t)dw.grid);
+        sw.scal = q;
+        sw.host_scal = dw.host_scal;
+        sw.grid = dw.grid;
+        sw.front = dw.front;
+        sw.stream_x = dw.stream_x;
+        sw.wall_i = dw.wall_i;
+        d = &shadow;
+    }
+    CgWork& w = d->cg;
     SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, sigma, s));
     IterStats st;
     // status: 1 converged, 2 no convergence (maxit, or the FP64 floor), 3 breakdown
@@ -1049,8 +1123,9 @@ sld_status cg_solve_impl(sld_disc d, const double* b, double* p, const sld_cg_pa
         // the launch that ran iteration k read the buffers of parity (k - seg0) & 1
         int seg0 = 0;
         while (true) {
-            sld_status e = run_iterations(d, false, shift, prm->graph_block, prm->profile != 0, s,
-                                          w.scal, w.host_scal, &st);
+            sld_status e = ws ? run_plain(d, prm->graph_block, s, w.scal, w.host_scal, &st)
+                              : run_iterations(d, false, shift, prm->graph_block,
+                                               prm->profile != 0, s, w.scal, w.host_scal, &st);
             if (e != SLD_OK) return e;
             rr = w.host_scal[S::RR];
             bb = w.host_scal[S::BB];
@@ -1212,6 +1287,28 @@ extern "C" {
 sld_status sld_cg_solve(sld_disc d, const double* b, double* p, const sld_cg_params* prm,
                         sld_cg_report* rep, void* stream) {
     return cg_solve_impl(d, b, p, prm, rep, stream, 0.0);
+}
+
+sld_status sld_cg_solve_static(sld_disc d, const double* b, double* p, const sld_cg_params* prm,
+                               sld_cg_report* rep, void* stream) {
+    SLD_REQUIRE(d && b && p && prm, SLD_E_INVALID, "sld_cg_solve_static: NULL argument");
+    SLD_REQUIRE_DEVICE(d, "sld_cg_solve_static");
+    DeviceGuard dg(d->mesh->device);
+    double* ws = nullptr;
+    SLD_HIP_CHECK(cg_static_scratch(d->mesh->device, &ws));
+    const int64_t n = d->mesh->ne * d->nphi;
+    const size_t need = static_ws_doubles(n, d->cg.grid);
+    if (need > kStaticCgDoubles) {
+        const int64_t fixed = (int64_t)static_ws_doubles(0, d->cg.grid);
+        sld_set_error("sld_cg_solve_static: the CG workspace of this disc (" +
+                      std::to_string(need) + " doubles for " + std::to_string(n) +
+                      " DOFs) exceeds the static workspace of " +
+                      std::to_string(kStaticCgDoubles) + " doubles (64 MiB); at most about " +
+                      std::to_string(((int64_t)kStaticCgDoubles - fixed) / 9) +
+                      " DOFs fit (ne * N_phi)");
+        return SLD_E_BUDGET;
+    }
+    return cg_solve_impl(d, b, p, prm, rep, stream, 0.0, ws);
 }
 
 }  // extern "C"

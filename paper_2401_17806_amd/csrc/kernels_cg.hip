@@ -18,6 +18,8 @@
 // through in-kernel atomics: every block sums the previous launch's partials itself in a
 // fixed order, so all blocks take bitwise identical decisions and results are deterministic.
 // The iteration counter is double-buffered by parity for the same reason.
+#include <mutex>
+
 #include "device_common.h"
 
 using namespace sld_dev;
@@ -836,6 +838,33 @@ __global__ __launch_bounds__(kBlockFlat) void k_rep_scal(const double* __restric
         }
     }
 }
+
+// ---------------------------------------------------------------- static CG workspace
+// The workspace of sld_cg_solve_static, for callers that cannot allocate device memory: one
+// array per device, held from the library's first use on that device until the process ends.
+// In host code `scratch` names a host-side stand-in: only the address that hipGetSymbolAddress
+// returns for the current device may be passed to kernels or copies.
+static __device__ __align__(256) double scratch[kStaticCgDoubles];
+
+}  // namespace
+
+hipError_t cg_static_scratch(int device, double** out) {
+    static std::mutex mu;
+    static double* ptr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (ptr[device] == nullptr) {
+        // the caller has made `device` current
+        void* a = nullptr;
+        hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[device] = static_cast<double*>(a);
+    }
+    *out = ptr[device];
+    return hipSuccess;
+}
+
+namespace {
 
 template <int P>
 const RefOps<P>* ops_of(const sld_disc_s* d) { return reinterpret_cast<const RefOps<P>*>(d->ops_dev); }

@@ -154,6 +154,11 @@ hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hi
 hipError_t launch_cg_replace(const sld_disc_s* d, int src, double sigma, hipStream_t s);
 // x += e, e = 0 (FP64 CG, before the solution is read)
 hipError_t launch_cg_fold(const sld_disc_s* d, hipStream_t s);
+// Static CG workspace of sld_cg_solve_static: kStaticCgDoubles doubles (64 MiB) per device, its
+// device address looked up once per device (the device must be current).
+constexpr size_t kStaticCgDoubles = size_t(8) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t cg_static_scratch(int device, double** out);
 // Dirichlet wall flags of the next diffusion solve from a per-edge mask (device [nd], NULL none)
 hipError_t launch_wall_mask(const sld_disc_s* d, const unsigned char* edge_mask, hipStream_t s);
 hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s);

@@ -93,6 +93,8 @@ _sig("sld_pressure_rhs", [_vp, _vp, ctypes.c_double, _vp, _vp])
 _sig("sld_velocity_correct", [_vp, _vp, _vp, ctypes.c_double, _vp, _vp])
 _sig("sld_cg_solve", [_vp, _vp, _vp, ctypes.POINTER(sld_cg_params),
                       ctypes.POINTER(sld_cg_report), _vp])
+_sig("sld_cg_solve_static", [_vp, _vp, _vp, ctypes.POINTER(sld_cg_params),
+                             ctypes.POINTER(sld_cg_report), _vp])
 _sig("sld_disc_footprint", [_vp, ctypes.POINTER(ctypes.c_uint64)])
 _sig("sld_ref_operator", [_vp, _i32, _i32, _c_dp, _i64, ctypes.POINTER(_i64)])
 _sig("sld_sl_advect", [_vp, _vp, _vp, _i32, ctypes.c_double, _vp, _vp])
@@ -121,7 +123,8 @@ EXPORTED = [
     "sld_last_error", "sld_abi_version", "sld_mesh_create", "sld_mesh_counts", "sld_mesh_edges",
     "sld_mesh_destroy", "sld_disc_create", "sld_disc_info", "sld_main_nodes", "sld_dual_nodes",
     "sld_main_weights", "sld_disc_destroy", "sld_schur_apply", "sld_gradient", "sld_divergence",
-    "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_disc_footprint",
+    "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_cg_solve_static",
+    "sld_disc_footprint",
     "sld_sl_advect", "sld_ref_operator", "sld_dual_to_main", "sld_main_to_dual",
     "sld_viscous_solve", "sld_state_create", "sld_state_destroy", "sld_imex_step",
     "sld_boussinesq_step",
@@ -372,6 +375,21 @@ class Disc:
         st = _lib.sld_cg_solve(self.handle, self._dev(b, self.main_shape, "b"),
                                self._dev(p, self.main_shape, "p"), ctypes.byref(prm),
                                ctypes.byref(rep), self._stream(stream))
+        report = report_dict(rep, st)
+        if st not in (0, 5):
+            _check(st)
+        return p, report
+
+    def sld_cg_solve_static(self, b, p=None, rtol=1e-12, maxit=100000, warm_start=False,
+                            graph_block=32, stream=None):
+        """sld_cg_solve in FP64 with its workspace in the library's static device array (no
+        device allocation in the call; p must be given to allocate nothing at all)."""
+        p = self._new(self.main_shape) if p is None else p
+        prm = make_params(rtol, maxit, warm_start, graph_block, False, "fp64", 0.5, 1)
+        rep = sld_cg_report()
+        st = _lib.sld_cg_solve_static(self.handle, self._dev(b, self.main_shape, "b"),
+                                      self._dev(p, self.main_shape, "p"), ctypes.byref(prm),
+                                      ctypes.byref(rep), self._stream(stream))
         report = report_dict(rep, st)
         if st not in (0, 5):
             _check(st)
