@@ -101,7 +101,8 @@ def step_flops_per_tri(p: int) -> int:
     return 2 * fma
 
 
-KERNEL_SOURCES = ("kernels_cg.hip", "device_common.h", "refops.h", "sld_internal.h")
+KERNEL_SOURCES = ("kernels_cg.hip", "kernels_mx.hip", "mx.h", "device_common.h", "refops.h",
+                  "sld_internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -139,8 +140,7 @@ def cpu_baseline(wl, workload, lattice_mesh, random_fourier_field, iters=100, sa
     and right-hand-side recipe; the oracle's assembly of the full 512x512x2 system alone takes
     several minutes).  A CG iteration costs the same per DOF at any mesh size, so the rate is in
     the metric's unit.  Timed twice: with the oracle's own sparse product (one thread), and with
-    the CSR product on every visible core (torch's CPU kernel), the vector updates unchanged."""
-    import torch
+    that product split into row blocks over every visible core (the vector updates unchanged)."""
     from oracle import solve
     from oracle.mesh import OracleMesh
     from oracle.operators import OracleDisc
@@ -159,14 +159,7 @@ def cpu_baseline(wl, workload, lattice_mesh, random_fourier_field, iters=100, sa
         cores = os.cpu_count()
     ne, nphi = b.shape
     _, info1 = solve.cg(K, b, tol=1e-30, maxit=iters)
-    nthreads0 = torch.get_num_threads()
-    torch.set_num_threads(cores)
-    Kt = torch.sparse_csr_tensor(torch.from_numpy(K.indptr.astype(np.int64)),
-                                 torch.from_numpy(K.indices.astype(np.int64)),
-                                 torch.from_numpy(K.data), size=K.shape)
-    _, infon = solve.cg(K, b, tol=1e-30, maxit=iters,
-                        matvec=lambda v: (Kt @ torch.from_numpy(v)).numpy())
-    torch.set_num_threads(nthreads0)
+    _, infon = solve.cg(K, b, tol=1e-30, maxit=iters, matvec=solve.row_block_matvec(K, cores))
     rate1 = ne * nphi * info1["iters"] / info1["seconds"]
     raten = ne * nphi * infon["iters"] / infon["seconds"]
     return {"value": raten, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
@@ -452,6 +445,9 @@ def main():
                          "the pressure solve; for --imex / --cavity, whose short viscous solves "
                          "would run more launches past convergence, 128 on meshes of n >= 64 "
                          "and 64 below")
+    ap.add_argument("--engine", choices=("auto", "valu", "mfma"), default="auto",
+                    help="reference contractions of the pressure iterations: the library's "
+                         "choice, the vector units, or the matrix cores")
     ap.add_argument("--inner-rtol", type=float, default=0.5,
                     help="mixed: residual reduction of the FP32 process between FP64 refreshes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -522,7 +518,7 @@ def main():
         disc.sld_pressure_rhs(vstar, 1.0 / coef, out=b)
         _, rep = disc.sld_cg_solve(b, p=pres, rtol=args.rtol, graph_block=args.graph_block,
                                    profile=profile and precision == "fp64", precision=precision,
-                                   inner_rtol=args.inner_rtol, maxit=200000)
+                                   inner_rtol=args.inner_rtol, maxit=200000, engine=args.engine)
         disc.sld_velocity_correct(vstar, pres, coef, out=vnew)
         return rep
 

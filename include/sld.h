@@ -134,6 +134,19 @@ void sld_disc_destroy(sld_disc disc);
  * in the paper's sign (K is symmetric negative semi-definite; K 1 = 0).  Wall edges do
  * not couple (K sums over interior edges).  p, Kp: device [ne][N_phi]; must not alias. */
 sld_status sld_schur_apply(sld_disc disc, const double* p, double* Kp, void* stream);
+/* sld_schur_apply_mx: the same K p (eq. pressure_final) with its reference contractions on the
+ * matrix cores (Section 3.4.1: every triangle's blocks are the same reference matrices times its
+ * geometry, so a tile of triangles contracts as two matrix products, MFMA).  Meshes without wall
+ * edges (periodic boxes) only: SLD_E_INVALID otherwise.
+ *   engine 0 (SLD_MX_F64): p, Kp device float64 [ne][N_phi], FP64 MFMA (v_mfma_f64_16x16x4);
+ *   engine 1 (SLD_MX_BF16X3): p, Kp device float32 [ne][N_phi], the FP32 operator of the
+ *     mixed-precision solve: BF16 MFMA (v_mfma_f32_16x16x32_bf16) on three-term bfloat16
+ *     splits of both operands (24 bits, the six products above 2^-24 kept) accumulated in
+ *     FP32, FP32 pointwise work on FP64-formed geometry.
+ * Uses the disc's CG workspace as staging: must not overlap a solve on the same disc.  p and
+ * Kp must not alias. */
+enum { SLD_MX_F64 = 0, SLD_MX_BF16X3 = 1 };
+sld_status sld_schur_apply_mx(sld_disc disc, const void* p, void* Kp, int32_t engine, void* stream);
 /* sld_gradient: ghat_j = Mhat_j^{-1} (Q_{l(j),j} p_l + Q_{r(j),j} p_r) (eq. ad4.2, lambda = 1).
  * p device [ne][N_phi] -> g device [nd][2][N_psi]; zero on wall edges. */
 sld_status sld_gradient(sld_disc disc, const double* p, double* g, void* stream);
@@ -210,6 +223,12 @@ typedef struct {
                              the FP32 process restarts).  Stops at rtol on the FP64 residual,
                              or when it no longer improves (rounding floor) */
     int32_t max_outer;    /* mixed only: cap on reliable updates */
+    int32_t engine;       /* reference contractions of the pressure iterations: 1 = the vector
+                             units; 2 = the matrix cores (FP64 MFMA for FP64 iterations, BF16x3
+                             MFMA for the FP32 inner iterations; see sld_schur_apply_mx) on
+                             meshes without wall edges, the vector units otherwise; 0 = the
+                             library's choice per precision (the faster form measured on the
+                             512x512x2, p = 3 mesh).  Viscous solves use the vector units. */
 } sld_cg_params;
 
 typedef struct {

@@ -170,6 +170,26 @@ def cg(K: sp.csr_matrix, b: np.ndarray, tol: float = 1e-12, maxit: int = 100000,
     return x.reshape(shape), info
 
 
+def row_block_matvec(K: sp.csr_matrix, nthreads: int):
+    """v -> K v computed as nthreads row blocks of K on a thread pool (scipy's sparse product
+    releases the interpreter lock): the same per-row sums as K @ v, bitwise, on several cores."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = K.shape[0]
+    nb = max(1, int(nthreads))
+    bounds = np.linspace(0, n, nb + 1).astype(np.int64)
+    blocks = [K[bounds[i]:bounds[i + 1]] for i in range(nb)]
+    pool = ThreadPoolExecutor(nb)
+
+    def matvec(v):
+        out = np.empty(n, dtype=np.result_type(K.dtype, v.dtype))
+
+        def one(i):
+            out[bounds[i]:bounds[i + 1]] = blocks[i] @ v
+        list(pool.map(one, range(nb)))
+        return out
+    return matvec
+
+
 def dense_bordered_solve(K: sp.csr_matrix, b: np.ndarray) -> np.ndarray:
     """Tiny meshes: solve [[-K, 1], [1^T, 0]] [p; lam] = [-b; 0] by LU (numpy)."""
     n = K.shape[0]

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsld.so")
 
 SOURCES = ["api.cpp", "refops.cpp", "server.cpp", "kernels_ops.hip", "kernels_cg.hip",
-           "kernels_sl.hip", "kernels_imex.hip"]
+           "kernels_sl.hip", "kernels_imex.hip", "kernels_mx.hip"]
 
 # Packed FP32 instructions are disabled for every HIP compile of this project.
 HIP_FLAGS = [

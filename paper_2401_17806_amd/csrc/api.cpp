@@ -204,6 +204,7 @@ void free_disc(sld_disc_s* d) {
     if (w.graph32) (void)hipGraphExecDestroy(w.graph32);
     dfree(d->ops32_dev);
     dfree(d->sl_dev);
+    dfree(d->mx_dev);
     dfree(w.scal);
     dfree(w.wall_i);
     if (w.graph) (void)hipGraphExecDestroy(w.graph);
@@ -232,7 +233,7 @@ extern "C" {
 
 const char* sld_last_error(void) { return g_err.c_str(); }
 
-int32_t sld_abi_version(void) { return 1; }
+int32_t sld_abi_version(void) { return 2; }
 
 sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int64_t ne,
                            const double* period, int32_t device, sld_mesh* out) {
@@ -583,6 +584,29 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         const int cap = std::atoi(gcap);
         if (cap > 0 && cap < G) G = (cap + 7) & ~7;
     }
+    // the MFMA operator serves meshes without wall edges (SLD_MX=0 in the environment turns it
+    // off, a debugging aid): its CG kernel sets the grid, as many blocks as stay resident (a
+    // multiple of 8), or one tile per block when the mesh has fewer tiles
+    w.mx_ok = m->periodic;
+    if (const char* mx = std::getenv("SLD_MX"))
+        if (std::atoi(mx) == 0) w.mx_ok = false;
+    if (w.mx_ok) {
+        int cus = 0;
+        const int per = mx_blocks_per_cu(d, false);
+        if (per > 0 && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) ==
+                           hipSuccess && cus > 0) {
+            const int64_t tiles = (m->ne + kTriPerBlock - 1) / kTriPerBlock;
+            int64_t g = std::min<int64_t>(tiles, (int64_t)per * cus);
+            g = std::min<int64_t>(g, kCgMaxGrid);
+            G = (int)((g + 7) & ~int64_t(7));
+        } else {
+            w.mx_ok = false;
+        }
+    }
+    if (const char* gcap = std::getenv("SLD_CG_GRID")) {
+        const int cap = std::atoi(gcap);
+        if (cap > 0 && cap < G) G = (cap + 7) & ~7;
+    }
     w.grid = G;
     if (const char* sx = std::getenv("SLD_CG_STREAM_X"))  // debugging aid: force x streaming
         w.stream_x = std::atoi(sx) != 0 ? 1 : 0;
@@ -596,9 +620,16 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         sld_set_error("sld_disc_create: semi-Lagrangian projection data failed to build");
         return SLD_E_INVALID;
     }
+    std::vector<unsigned char> hmx(mx_tab_bytes(p));
+    if (build_mx_tables(p, d->ops_host, hmx.data()) != 0) {
+        free_disc(d);
+        sld_set_error("sld_disc_create: MFMA operand tables failed to build");
+        return SLD_E_INVALID;
+    }
     hipError_t e = up.err;
     if (e == hipSuccess) e = hipMalloc(&d->ops_dev, d->ops_bytes);
     if (e == hipSuccess) e = hipMalloc(&d->ops32_dev, h32.size());
+    if (e == hipSuccess) e = hipMalloc(&d->mx_dev, hmx.size());
     if (e == hipSuccess) e = hipMalloc(&d->sl_dev, hsl.size());
     if (e == hipSuccess) e = dalloc(&w.x, nv);
     if (e == hipSuccess) e = dalloc(&w.e, nv);
@@ -624,6 +655,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         up.copy(d->ops_dev, d->ops_host, d->ops_bytes);
         up.copy(d->ops32_dev, h32.data(), h32.size());
         up.copy(d->sl_dev, hsl.data(), hsl.size());
+        up.copy(d->mx_dev, hmx.data(), hmx.size());
         up.zero(w.scal, CgScalars::NSCAL * sizeof(double));
         up.zero(w.wall_i, size_t(m->ne));
         up.zero(w.scal_in, CgScalars::NSCAL * sizeof(double));
@@ -803,6 +835,19 @@ sld_status sld_schur_apply(sld_disc d, const double* p, double* Kp, void* stream
     return SLD_OK;
 }
 
+sld_status sld_schur_apply_mx(sld_disc d, const void* p, void* Kp, int32_t engine, void* stream) {
+    SLD_REQUIRE(d && p && Kp, SLD_E_INVALID, "sld_schur_apply_mx: NULL argument");
+    SLD_REQUIRE(p != Kp, SLD_E_INVALID, "sld_schur_apply_mx: p and Kp must not alias");
+    SLD_REQUIRE(engine == SLD_MX_F64 || engine == SLD_MX_BF16X3, SLD_E_INVALID,
+                "sld_schur_apply_mx: engine must be SLD_MX_F64 or SLD_MX_BF16X3");
+    SLD_REQUIRE_DEVICE(d, "sld_schur_apply_mx");
+    SLD_REQUIRE(d->mx_dev && d->mesh->periodic, SLD_E_INVALID,
+                "sld_schur_apply_mx: the MFMA operator runs on meshes without wall edges");
+    DeviceGuard dg(d->mesh->device);
+    SLD_HIP_CHECK(launch_apply_mx(d, p, Kp, engine == SLD_MX_BF16X3, (hipStream_t)stream));
+    return SLD_OK;
+}
+
 sld_status sld_gradient(sld_disc d, const double* p, double* g, void* stream) {
     SLD_REQUIRE(d && p && g, SLD_E_INVALID, "sld_gradient: NULL argument");
     SLD_REQUIRE_DEVICE(d, "sld_gradient");
@@ -854,6 +899,11 @@ sld_status sld_sl_advect(sld_disc d, const double* vbar, const double* q, int32_
 }  // extern "C"
 
 namespace {
+
+// engine 0 (the library's choice): whether the pressure iterations of each precision run on the
+// matrix cores, by the measured time per iteration on the 512x512x2, p = 3 mesh
+constexpr bool kAutoMx64 = false;
+constexpr bool kAutoMx32 = false;
 
 // Capture one block of gb CG iterations (FP64, FP64 mass-shifted, or the FP32 inner solve)
 // into a graph.  The FP32 block ends with the peek at its process's recursive rr, so that the
@@ -917,9 +967,11 @@ sld_status run_iterations(sld_disc_s* d, bool fp32, bool shift, int gb, bool pro
         w.events.assign(6, nullptr);
         for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
     }
-    if (graph == nullptr || graph_block != gb) {
+    bool& gmx = w.graph_mx[fp32 ? 2 : (shift ? 1 : 0)];
+    if (graph == nullptr || graph_block != gb || gmx != w.use_mx) {
         SLD_HIP_CHECK(capture_block(d, fp32, shift, gb, &graph));
         graph_block = gb;
+        gmx = w.use_mx;
     }
     const int kind = shift ? 1 : 0;
     int expect = 0;  // fewest blocks among the recorded solves (0: none recorded)
@@ -985,9 +1037,10 @@ sld_status run_iterations(sld_disc_s* d, bool fp32, bool shift, int gb, bool pro
 sld_status run_block(sld_disc_s* d, int gb, hipStream_t s, IterStats* st) {
     typedef CgScalars S;
     CgWork& w = d->cg;
-    if (w.graph32 == nullptr || w.graph32_block != gb) {
+    if (w.graph32 == nullptr || w.graph32_block != gb || w.graph_mx[2] != w.use_mx) {
         SLD_HIP_CHECK(capture_block(d, true, false, gb, &w.graph32));
         w.graph32_block = gb;
+        w.graph_mx[2] = w.use_mx;
     }
     SLD_HIP_CHECK(hipGraphLaunch(w.graph32, s));
     SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal_in, w.scal_in, S::NSCAL * sizeof(double),
@@ -1075,6 +1128,7 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
         shadow.npsi = d_in->npsi;
         shadow.ops_dev = d_in->ops_dev;
         shadow.ops_bytes = d_in->ops_bytes;
+        shadow.mx_dev = d_in->mx_dev;
         CgWork& sw = shadow.cg;
         const CgWork& dw = d_in->cg;
         const int64_t n = d_in->mesh->ne * d_in->nphi;
@@ -1097,9 +1151,14 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
         sw.front = dw.front;
         sw.stream_x = dw.stream_x;
         sw.wall_i = dw.wall_i;
+        sw.mx_ok = dw.mx_ok;
         d = &shadow;
     }
     CgWork& w = d->cg;
+    SLD_REQUIRE(prm->engine >= 0 && prm->engine <= 2, SLD_E_INVALID,
+                "sld_cg_solve: engine must be 0 (library's choice), 1 (vector units) or 2 "
+                "(matrix cores)");
+    w.use_mx = w.mx_ok && (prm->engine == 2 || (prm->engine == 0 && (mixed ? kAutoMx32 : kAutoMx64)));
     SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, sigma, s));
     IterStats st;
     // status: 1 converged, 2 no convergence (maxit, or the FP64 floor), 3 breakdown

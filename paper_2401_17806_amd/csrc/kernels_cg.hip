@@ -950,6 +950,7 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
     const bool sx = stream_x_for(d, sizeof(double)) != 0;
+    if (!shift && w.use_mx) return launch_cg_step_mx(d, parity, false, sx, s);
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double), front);
 #define SLD_STEP64(F, SH, ST)                                                                   \
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, double, RefOps<PP>, F, SH, ST>), dim3(G), \
@@ -1052,6 +1053,7 @@ hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
     const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float), front);
     const bool sx = stream_x_for(d, sizeof(float)) != 0;
+    if (w.use_mx) return launch_cg_step_mx(d, parity, true, sx, s);
 #define SLD_STEP32(F, ST)                                                                       \
     SLD_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step<PP, float, RefOps32<PP>, F, false, ST>), dim3(G), \
                                           dim3(F ? kBlockCG : kBlockTri), lds, s, ops32_of<PP>(d), \

@@ -100,6 +100,12 @@ struct CgWork {
     int graph_block = 0;             // iterations in `graph`
     hipGraphExec_t graph_shift = nullptr;  // the same for the viscous (mass-shifted) system
     int graph_shift_block = 0;
+    // MFMA operator (kernels_mx.hip): available on meshes without wall edges (mx_ok); used by the
+    // pressure and FP32 inner iterations of the current solve when use_mx; the graphs above were
+    // captured with graph_mx[fp64, shift, fp32]
+    bool mx_ok = false;
+    bool use_mx = false;
+    bool graph_mx[3] = {false, false, false};
 };
 
 struct sld_disc_s {
@@ -109,6 +115,7 @@ struct sld_disc_s {
     void* ops_host = nullptr;      // RefOps<p> on the host
     void* ops32_dev = nullptr;     // RefOps32<p> on the device (mixed precision)
     void* sl_dev = nullptr;        // SlOps<p> on the device (semi-Lagrangian projection)
+    void* mx_dev = nullptr;        // MxTab<p> on the device (MFMA operands of the operator)
     size_t ops_bytes = 0;
     CgWork cg;
 };
@@ -168,6 +175,16 @@ hipError_t launch_rel_restart(const sld_disc_s* d, hipStream_t s);
 hipError_t launch_sl_advect(const sld_disc_s* d, const double* vbar, const double* q, int nc,
                             double dt, double* out, hipStream_t s);
 hipError_t launch_rel_peek(const sld_disc_s* d, int resume, hipStream_t s);
+// MFMA operator (kernels_mx.hip): table size and construction from RefOps<p> (host), LDS bytes
+// of its kernels, standalone apply in caller order (f32: float in/out with the BF16x3 engine,
+// else FP64), one CG iteration (the pressure or FP32 inner iteration of k_cg_step), resident
+// blocks per CU of its CG kernel
+size_t mx_tab_bytes(int p);
+int build_mx_tables(int p, const void* refops, void* out);
+size_t mx_lds_bytes(int p, int hmax, size_t word);
+hipError_t launch_apply_mx(const sld_disc_s* d, const void* p, void* out, bool f32, hipStream_t s);
+hipError_t launch_cg_step_mx(const sld_disc_s* d, int parity, bool f32, bool stream_x, hipStream_t s);
+int mx_blocks_per_cu(const sld_disc_s* d, bool f32);
 // grid transfers and the viscous right-hand side (kernels_imex.hip); strides in doubles
 hipError_t launch_dual_to_main(const sld_disc_s* d, const double* vd, int nc, double* out,
                                int64_t o_is, int64_t o_cs, hipStream_t s);

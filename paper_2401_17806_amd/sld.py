@@ -37,7 +37,7 @@ _i32 = ctypes.c_int32
 class sld_cg_params(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("maxit", _i32),
                 ("warm_start", _i32), ("graph_block", _i32), ("profile", _i32),
-                ("precision", _i32), ("max_outer", _i32)]
+                ("precision", _i32), ("max_outer", _i32), ("engine", _i32)]
 
 
 class sld_cg_report(ctypes.Structure):
@@ -87,6 +87,7 @@ _sig("sld_dual_nodes", [_vp, _c_dp])
 _sig("sld_main_weights", [_vp, _c_dp])
 _sig("sld_disc_destroy", [_vp], None)
 _sig("sld_schur_apply", [_vp, _vp, _vp, _vp])
+_sig("sld_schur_apply_mx", [_vp, _vp, _vp, _i32, _vp])
 _sig("sld_gradient", [_vp, _vp, _vp, _vp])
 _sig("sld_divergence", [_vp, _vp, _vp, _vp])
 _sig("sld_pressure_rhs", [_vp, _vp, ctypes.c_double, _vp, _vp])
@@ -122,7 +123,8 @@ _sig("sld_server_destroy", [_vp], None)
 EXPORTED = [
     "sld_last_error", "sld_abi_version", "sld_mesh_create", "sld_mesh_counts", "sld_mesh_edges",
     "sld_mesh_destroy", "sld_disc_create", "sld_disc_info", "sld_main_nodes", "sld_dual_nodes",
-    "sld_main_weights", "sld_disc_destroy", "sld_schur_apply", "sld_gradient", "sld_divergence",
+    "sld_main_weights", "sld_disc_destroy", "sld_schur_apply", "sld_schur_apply_mx", "sld_gradient",
+    "sld_divergence",
     "sld_pressure_rhs", "sld_velocity_correct", "sld_cg_solve", "sld_cg_solve_static",
     "sld_disc_footprint",
     "sld_sl_advect", "sld_ref_operator", "sld_dual_to_main", "sld_main_to_dual",
@@ -213,13 +215,18 @@ def sld_disc_destroy(h):
     _lib.sld_disc_destroy(h)
 
 
+ENGINES = {"auto": 0, "valu": 1, "mfma": 2}
+
+
 def make_params(rtol=1e-12, maxit=100000, warm_start=False, graph_block=32, profile=False,
-                precision="fp64", inner_rtol=0.5, max_outer=1000):
+                precision="fp64", inner_rtol=0.5, max_outer=1000, engine="auto"):
     if precision not in ("fp64", "mixed"):
         raise ValueError("precision must be 'fp64' or 'mixed'")
+    if engine not in ENGINES:
+        raise ValueError("engine must be 'auto' (the library's choice), 'valu' or 'mfma'")
     return sld_cg_params(float(rtol), float(inner_rtol), int(maxit), int(bool(warm_start)),
                          int(graph_block), int(bool(profile)), 1 if precision == "mixed" else 0,
-                         int(max_outer))
+                         int(max_outer), ENGINES[engine])
 
 
 def report_dict(rep, st):
@@ -305,6 +312,23 @@ class Disc:
                                     self._dev(out, self.main_shape, "Kp"), self._stream(stream)))
         return out
 
+    def sld_schur_apply_mx(self, p, engine="f64", out=None, stream=None):
+        """K p on the matrix cores: engine "f64" (float64 tensors) or "bf16x3" (float32)."""
+        import torch
+        code = {"f64": 0, "bf16x3": 1}[engine]
+        dt = torch.float64 if code == 0 else torch.float32
+        if out is None:
+            out = torch.empty(self.main_shape, dtype=dt, device=f"cuda:{self.mesh.device}")
+        for name, t in (("p", p), ("Kp", out)):
+            if (not isinstance(t, torch.Tensor) or t.dtype != dt or not t.is_cuda
+                    or t.device.index != self.mesh.device or tuple(t.shape) != self.main_shape
+                    or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous {dt} tensor {self.main_shape} "
+                                 f"on cuda:{self.mesh.device}")
+        _check(_lib.sld_schur_apply_mx(self.handle, _vp(p.data_ptr()), _vp(out.data_ptr()), code,
+                                       self._stream(stream)))
+        return out
+
     def sld_gradient(self, p, out=None, stream=None):
         out = self._new(self.dual_shape) if out is None else out
         _check(_lib.sld_gradient(self.handle, self._dev(p, self.main_shape, "p"),
@@ -366,11 +390,13 @@ class Disc:
 
     def sld_cg_solve(self, b, p=None, rtol=1e-12, maxit=100000, warm_start=False,
                      graph_block=32, profile=False, precision="fp64", inner_rtol=0.5,
-                     max_outer=1000, stream=None):
-        """Solve K p = b (gauge int p = 0).  precision: "fp64" or "mixed"."""
+                     max_outer=1000, stream=None, engine="auto"):
+        """Solve K p = b (gauge int p = 0).  precision: "fp64" or "mixed"; engine: "auto" (the
+        library's choice), "valu" (vector units) or "mfma" (matrix cores where the mesh has no
+        walls)."""
         p = self._new(self.main_shape) if p is None else p
         prm = make_params(rtol, maxit, warm_start, graph_block, profile, precision, inner_rtol,
-                          max_outer)
+                          max_outer, engine)
         rep = sld_cg_report()
         st = _lib.sld_cg_solve(self.handle, self._dev(b, self.main_shape, "b"),
                                self._dev(p, self.main_shape, "p"), ctypes.byref(prm),

@@ -6,8 +6,9 @@ dual nodes; b = (1/(a_ss dt)) D v* with dt = 0.5 h, h = 2 pi / 512, a_ss = the S
 diagonal (eq. pressure_IMEX without sources); CG on -K to 1e-12 (eq. pressure_final, plain
 matrix-free CG of Section 3.3 in its assembled oracle form); gauge int p = 0.
 
-    python tests/golden/make_c3_sample.py [full_out.npy]   (about two hours on one core,
-                                                             about 20 GB of memory)
+    python tests/golden/make_c3_sample.py [full_out.npy]   (about 20 GB of memory; the CG's
+        sparse product K v runs as row blocks of the oracle's own product on every visible core,
+        bitwise the same sums; about two hours on one core)
 """
 import math
 import os
@@ -38,7 +39,8 @@ def main():
     print(f"rhs done {time.perf_counter() - t0:.0f} s", flush=True)
     K = solve.assemble_K(od)
     print(f"K assembled, nnz {K.nnz}, {time.perf_counter() - t0:.0f} s", flush=True)
-    x, info = solve.cg(K, b, tol=1e-12, maxit=400000)
+    x, info = solve.cg(K, b, tol=1e-12, maxit=400000,
+                       matvec=solve.row_block_matvec(K, len(os.sched_getaffinity(0))))
     print(f"cg {info}, {time.perf_counter() - t0:.0f} s", flush=True)
     x = solve.gauge(od, x)
     bp = solve.project_mean(b).ravel()
