@@ -249,7 +249,7 @@ def _hodge_error(n, p):
     return np.sqrt(((x - phi_m(d.main_node_xy())) ** 2).mean())
 
 
-@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_pressure_of_gradient_field_converges(p):
     """Helmholtz-Hodge closed form: for v* = grad phi_m, phi_m = cos 2x + cos 2y (zero mean),
     the pressure of eq. pressure_final with b = D v* converges to phi_m at order about p + 1."""
