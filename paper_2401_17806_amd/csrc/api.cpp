@@ -585,22 +585,29 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         if (cap > 0 && cap < G) G = (cap + 7) & ~7;
     }
     // the MFMA operator serves meshes without wall edges (SLD_MX=0 in the environment turns it
-    // off, a debugging aid): its CG kernel sets the grid, as many blocks as stay resident (a
-    // multiple of 8), or one tile per block when the mesh has fewer tiles
+    // off, a debugging aid).  When the library's default FP64 iteration is the MFMA one (or
+    // SLD_MX_GRID=1, a debugging aid for measuring it), its CG kernel sets the grid: as many
+    // blocks as stay resident (a multiple of 8), or one tile per block on smaller meshes.  The
+    // grid is shared by every CG kernel of the disc (the dot partials are laid out by it).
     w.mx_ok = m->periodic;
     if (const char* mx = std::getenv("SLD_MX"))
         if (std::atoi(mx) == 0) w.mx_ok = false;
+    bool mx_grid = kAutoMx64;
+    if (const char* mg = std::getenv("SLD_MX_GRID")) mx_grid = std::atoi(mg) != 0;
     if (w.mx_ok) {
+        // (resident blocks of the MFMA kernels, both word sizes: zero when the tile's LDS does
+        // not fit, and then the disc keeps the vector-unit kernels)
         int cus = 0;
         const int per = mx_blocks_per_cu(d, false);
-        if (per > 0 && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) ==
-                           hipSuccess && cus > 0) {
+        if (per <= 0 || mx_blocks_per_cu(d, true) <= 0 ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device) != hipSuccess ||
+            cus <= 0) {
+            w.mx_ok = false;
+        } else if (mx_grid) {
             const int64_t tiles = (m->ne + kTriPerBlock - 1) / kTriPerBlock;
             int64_t g = std::min<int64_t>(tiles, (int64_t)per * cus);
             g = std::min<int64_t>(g, kCgMaxGrid);
             G = (int)((g + 7) & ~int64_t(7));
-        } else {
-            w.mx_ok = false;
         }
     }
     if (const char* gcap = std::getenv("SLD_CG_GRID")) {
@@ -843,6 +850,9 @@ sld_status sld_schur_apply_mx(sld_disc d, const void* p, void* Kp, int32_t engin
     SLD_REQUIRE_DEVICE(d, "sld_schur_apply_mx");
     SLD_REQUIRE(d->mx_dev && d->mesh->periodic, SLD_E_INVALID,
                 "sld_schur_apply_mx: the MFMA operator runs on meshes without wall edges");
+    SLD_REQUIRE(d->cg.mx_ok, SLD_E_INVALID,
+                "sld_schur_apply_mx: the MFMA operator is off for this disc (its tile does not fit "
+                "the device, or SLD_MX=0)");
     DeviceGuard dg(d->mesh->device);
     SLD_HIP_CHECK(launch_apply_mx(d, p, Kp, engine == SLD_MX_BF16X3, (hipStream_t)stream));
     return SLD_OK;
@@ -899,11 +909,6 @@ sld_status sld_sl_advect(sld_disc d, const double* vbar, const double* q, int32_
 }  // extern "C"
 
 namespace {
-
-// engine 0 (the library's choice): whether the pressure iterations of each precision run on the
-// matrix cores, by the measured time per iteration on the 512x512x2, p = 3 mesh
-constexpr bool kAutoMx64 = false;
-constexpr bool kAutoMx32 = false;
 
 // Capture one block of gb CG iterations (FP64, FP64 mass-shifted, or the FP32 inner solve)
 // into a graph.  The FP32 block ends with the peek at its process's recursive rr, so that the

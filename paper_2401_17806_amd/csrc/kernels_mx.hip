@@ -29,6 +29,23 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 constexpr int kMxThreads = 256;
+// Tuning constants (compile time): halo entries per thread whose ids are requested one tile
+// ahead (larger halos take a plain loop for the rest); minimum waves per SIMD the CG kernel is
+// compiled for (the register budget); whether the edge stage reads the neighbour's geometry from
+// the per-edge copy (requested with the triangle's own) or through the neighbour's id.
+// Measured per FP64 / FP32 iteration on the 512x512x2, p = 3 mesh (the software-pipelined tile
+// loop below): two waves per SIMD and geometry through the id 134 / 120 us; with the per-edge
+// copy 141 / 116 us; three waves per SIMD spill registers to scratch, 251 / 204 us.
+#ifndef SLD_MX_HALO_PER
+#define SLD_MX_HALO_PER 3
+#endif
+#ifndef SLD_MX_WAVES
+#define SLD_MX_WAVES 2
+#endif
+#ifndef SLD_MX_GEONB
+#define SLD_MX_GEONB 0
+#endif
+constexpr int kHaloPer = SLD_MX_HALO_PER;
 constexpr int T = kTriPerBlock;  // 64 triangles per tile = 4 column blocks of 16
 
 // main index of node m (0..P) of local edge al (runtime al; see edge_node)
@@ -61,35 +78,57 @@ __device__ __forceinline__ int out_row(int g, int j) { return sizeof(Real) == 8 
 template <int P, typename Real>
 struct MxFrag;
 
+// (G1's operands stay in registers for the whole launch; G2's, the larger set, are requested
+// from the cache-resident table at the end of each tile's edge-node stage, so that they are not
+// live during the state update and G1.)
 template <int P>
 struct MxFrag<P, double> {
     using D = MxDims<P>;
+    const MxTab<P>* tab;
     double a1[2][D::KS1];
-    double a2[D::KS2];
-    __device__ __forceinline__ void load(const MxTab<P>* __restrict__ tab, int lane) {
+    __device__ __forceinline__ void load(const MxTab<P>* __restrict__ t, int lane) {
+        tab = t;
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-            for (int ks = 0; ks < D::KS1; ++ks) a1[rb][ks] = tab->a1[rb][ks][lane];
-#pragma unroll
-        for (int ks = 0; ks < D::KS2; ++ks) a2[ks] = tab->a2[ks][lane];
+            for (int ks = 0; ks < D::KS1; ++ks) a1[rb][ks] = t->a1[rb][ks][lane];
     }
 };
 
 template <int P>
 struct MxFrag<P, float> {
     using D = MxDims<P>;
+    const MxTab<P>* tab;
     bf8v a1[2][3];
-    bf8v a2[D::KS232][3];
-    __device__ __forceinline__ void load(const MxTab<P>* __restrict__ tab, int lane) {
+    __device__ __forceinline__ void load(const MxTab<P>* __restrict__ t, int lane) {
+        tab = t;
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-            for (int s = 0; s < 3; ++s) a1[rb][s] = load_bf8(&tab->b1[rb][s][lane][0]);
+            for (int s = 0; s < 3; ++s) a1[rb][s] = load_bf8(&t->b1[rb][s][lane][0]);
+    }
+};
+
+template <int P, typename Real>
+struct MxFrag2;
+
+template <int P>
+struct MxFrag2<P, double> {
+    double a2[MxDims<P>::KS2];
+    __device__ __forceinline__ void load(const MxTab<P>* __restrict__ t, int lane) {
 #pragma unroll
-        for (int ks = 0; ks < D::KS232; ++ks)
+        for (int ks = 0; ks < MxDims<P>::KS2; ++ks) a2[ks] = t->a2[ks][lane];
+    }
+};
+
+template <int P>
+struct MxFrag2<P, float> {
+    bf8v a2[MxDims<P>::KS232][3];
+    __device__ __forceinline__ void load(const MxTab<P>* __restrict__ t, int lane) {
 #pragma unroll
-            for (int s = 0; s < 3; ++s) a2[ks][s] = load_bf8(&tab->b2[ks][s][lane][0]);
+        for (int ks = 0; ks < MxDims<P>::KS232; ++ks)
+#pragma unroll
+            for (int s = 0; s < 3; ++s) a2[ks][s] = load_bf8(&t->b2[ks][s][lane][0]);
     }
 };
 
@@ -112,13 +151,45 @@ __device__ __forceinline__ void bf3_mma(const bf8v (&a)[3], const float (&bv)[8]
     hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], bh, hi, 0, 0, 0);
 }
 
-// LDS of one block, in words of Real: sd [(T + hmax) N] directions of the tile then its halo;
-// sr [T N] residuals (CG only); se [(T + hmax) R1] edge-node derivatives; sz [T KE] the edge
-// part of z.
+// LDS of one block, in words of Real, rows of odd stride (MxDims): sd [T + hmax][NS] directions
+// of the tile then its halo; sr [T][NS] residuals (CG only); se [T + hmax][R1S] edge-node
+// derivatives.
 template <int P>
 inline size_t mx_lds_words(int hmax) {
     using D = MxDims<P>;
-    return (size_t)(T + hmax) * D::N + (size_t)T * D::N + (size_t)(T + hmax) * D::R1 + (size_t)T * D::KE;
+    return (size_t)(T + hmax) * D::NS + (size_t)T * D::NS + (size_t)(T + hmax) * D::R1S;
+}
+
+// Per-thread geometry of one tile, requested before the tile's state so that its latency
+// overlaps the state loads and G1: lane (t, g) of wave w needs triangle t = 16 w + lane % 16, its
+// neighbour table and its neighbours' geometry (the per-edge copy, so no load waits for a
+// neighbour's id).
+struct MxPre {
+    int4 nb4;
+    double4 e, er[3];
+};
+
+__device__ __forceinline__ void mx_prefetch(const double4* __restrict__ geo,
+                                            const double4* __restrict__ geo_nb,
+                                            const int4* __restrict__ nbr, int64_t i0, int64_t ne,
+                                            MxPre& pre) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = i0 + 16 * wave + (lane & 15);
+    if (i < ne) {
+        pre.nb4 = nbr[i];
+        pre.e = geo[i];
+#if SLD_MX_GEONB
+#pragma unroll
+        for (int al = 0; al < 3; ++al) pre.er[al] = geo_nb[i * 3 + al];
+#else
+        (void)geo_nb;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            const int nb = pick(pre.nb4, al);
+            pre.er[al] = nb >= 0 ? geo[nb >> 2] : make_double4(0, 0, 0, 0);
+        }
+#endif
+    }
 }
 
 // The operator on one tile whose directions (tile then halo, zero where padded) are in sd:
@@ -126,14 +197,13 @@ inline size_t mx_lds_words(int hmax) {
 // (y[j] is row out_row<Real>(g, j).)  The caller separates the next tile's LDS writes from G2's
 // reads with a barrier.  Requires every edge to have a neighbour (no walls).
 template <int P, typename Real, class Ops>
-__device__ __forceinline__ void mx_tile_op(const Ops& R, const MxFrag<P, Real>& F,
-                                           const double4* __restrict__ geo,
-                                           const int4* __restrict__ nbr,
+__device__ __forceinline__ void mx_tile_op(const Ops& R, const MxFrag<P, Real>& F, const MxPre& pre,
                                            const int* __restrict__ halo_row, int hmax, int64_t i0,
-                                           int64_t ne, const Real* sd, Real* se, Real* sz,
+                                           int64_t ne, const Real* sd, Real* se,
                                            Real (&y)[4]) {
     using D = MxDims<P>;
-    constexpr int N = D::N, NE = D::NE, R1 = D::R1, KE = D::KE;
+    constexpr int N = D::N, NE = D::NE, R1 = D::R1;
+    constexpr int NS = D::NS, R1S = D::R1S;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
     const int nslots = T + hmax;
@@ -150,7 +220,7 @@ __device__ __forceinline__ void mx_tile_op(const Ops& R, const MxFrag<P, Real>& 
 #pragma unroll
             for (int ks = 0; ks < D::KS1; ++ks) {
                 const int l = 4 * ks + g;
-                const double b = (sv && l < N) ? (double)sd[slot * N + l] : 0.0;
+                const double b = (sv && l < N) ? (double)sd[slot * NS + l] : 0.0;
                 acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(F.a1[0][ks], b, acc0, 0, 0, 0);
                 acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(F.a1[1][ks], b, acc1, 0, 0, 0);
             }
@@ -158,8 +228,8 @@ __device__ __forceinline__ void mx_tile_op(const Ops& R, const MxFrag<P, Real>& 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int r0 = out_row<double>(g, j), r1 = 16 + r0;
-                    if (r0 < R1) se[slot * R1 + r0] = (Real)acc0[j];
-                    if (r1 < R1) se[slot * R1 + r1] = (Real)acc1[j];
+                    if (r0 < R1) se[slot * R1S + r0] = (Real)acc0[j];
+                    if (r1 < R1) se[slot * R1S + r1] = (Real)acc1[j];
                 }
             }
         } else {
@@ -167,7 +237,7 @@ __device__ __forceinline__ void mx_tile_op(const Ops& R, const MxFrag<P, Real>& 
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int l = 8 * g + e;
-                bv[e] = (sv && l < N) ? (float)sd[slot * N + l] : 0.0f;
+                bv[e] = (sv && l < N) ? (float)sd[slot * NS + l] : 0.0f;
             }
             f4v h0 = {0, 0, 0, 0}, l0 = {0, 0, 0, 0}, h1 = {0, 0, 0, 0}, l1 = {0, 0, 0, 0};
             bf3_mma(F.a1[0], bv, h0, l0);
@@ -176,107 +246,114 @@ __device__ __forceinline__ void mx_tile_op(const Ops& R, const MxFrag<P, Real>& 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int r0 = out_row<float>(g, j), r1 = 16 + r0;
-                    if (r0 < R1) se[slot * R1 + r0] = (Real)(h0[j] + l0[j]);
-                    if (r1 < R1) se[slot * R1 + r1] = (Real)(h1[j] + l1[j]);
+                    if (r0 < R1) se[slot * R1S + r0] = (Real)(h0[j] + l0[j]);
+                    if (r1 < R1) se[slot * R1S + r1] = (Real)(h1[j] + l1[j]);
                 }
             }
         }
     }
     __syncthreads();
-    // ---- edge nodes: wave al < 3 takes local edge al of tile triangle `lane`
-    if (wave < 3) {
-        const int al = wave;
-        const int t = lane;
-        const int64_t i = i0 + t;
-        if (i < ne) {
-            const int4 nb4 = nbr[i];
-            const int nb = pick(nb4, al);
-            const double4 e = geo[i];
-            Real* z = sz + t * KE + al * 3 * NE;
-            if (nb < 0) {
-                // (not reached: the host runs this operator on meshes without wall edges)
-#pragma unroll
-                for (int m = 0; m < 3 * NE; ++m) z[m] = Real(0);
-            } else {
-                const int slot = (nb4.w >> (10 * al)) & 1023;
-                const int ar = nb & 3;
-                const double4 er = geo[nb >> 2];
-                const Geo gd = make_geo(e.x, e.y, e.z, e.w);
-                const GeoR<Real> gg(gd);
-                const Geo grd = make_geo(er.x, er.y, er.z, er.w);
-                const GeoR<Real> gr(grd);
-                const Real wsum = (Real)(1.0 / (gd.A + grd.A));
-                // |Gamma| n, outward: the edge vector v_{al+1} - v_al turned clockwise
-                const double ex = al == 0 ? e.x : (al == 1 ? e.z - e.x : -e.z);
-                const double ey = al == 0 ? e.y : (al == 1 ? e.w - e.y : -e.w);
-                const Real snx = (Real)ey, sny = (Real)(-ex);
-                Real delta[NE];
-#pragma unroll
-                for (int m = 0; m < NE; ++m)
-                    delta[m] = sd[slot * N + edge_node_rt<P>(ar, P - m)] - sd[t * N + edge_node_rt<P>(al, m)];
-                const Real* dso = se + t * R1 + al * 2 * NE;
-                const Real* dsn = se + slot * R1 + ar * 2 * NE;
-#pragma unroll
-                for (int m = 0; m < NE; ++m) {
-                    const Real ds0 = dso[m], ds1 = dso[NE + m];
-                    const Real dn0 = dsn[P - m], dn1 = dsn[NE + P - m];
-                    const Real gsx = gg.G00 * ds0 + gg.G10 * ds1, gsy = gg.G01 * ds0 + gg.G11 * ds1;
-                    const Real gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
-                    Real cd = 0;
-#pragma unroll
-                    for (int q = 0; q < NE; ++q) cd = mad((Real)R.C[m][q], delta[q], cd);
-                    const Real hx = (gg.A * gsx + gr.A * gnx + Real(3) * snx * cd) * wsum;
-                    const Real hy = (gg.A * gsy + gr.A * gny + Real(3) * sny * cd) * wsum;
-                    const Real dx = hx - gsx, dy = hy - gsy;
-                    z[m] = snx * hx + sny * hy;
-                    z[NE + m] = -gg.A * (gg.G00 * dx + gg.G01 * dy);
-                    z[2 * NE + m] = -gg.A * (gg.G10 * dx + gg.G11 * dy);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // ---- G2: rows of (K d)_t, t = 16 wave + li
+    // ---- edge nodes, per wave and without a barrier before G2: lane (t, g) of wave w forms,
+    // for tile triangle t = 16 w + lane % 16 and its nodes m = g + 4 q on each edge al, the
+    // normal flux and the sub-triangle correction of the closed form of Mhat_j^{-1} (the same
+    // algebra as the vector-unit operator core), which are exactly its B operands of G2
     const int t = 16 * wave + li;
     const int64_t i = i0 + t;
-    Real cf[3] = {Real(0), Real(0), Real(0)};  // -A m00, -A m01, -A m11
+    constexpr int NQ = D::NQ;
+    Real z[NQ][9];  // [q][al * 3 + s]: s = 0 normal flux, 1 / 2 the two reference components
+    Real cf[3] = {Real(0), Real(0), Real(0)};  // -A m00, -A m01, -A m11 (volume term)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) z[q][c] = Real(0);
     if (i < ne) {
-        const double4 e = geo[i];
+        const double4 e = pre.e;
         const Geo gd = make_geo(e.x, e.y, e.z, e.w);
+        const GeoR<Real> gg(gd);
         cf[0] = (Real)(-gd.A * (gd.G00 * gd.G00 + gd.G01 * gd.G01));
         cf[1] = (Real)(-gd.A * (gd.G00 * gd.G10 + gd.G01 * gd.G11));
         cf[2] = (Real)(-gd.A * (gd.G10 * gd.G10 + gd.G11 * gd.G11));
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            const int nb = pick(pre.nb4, al);
+            if (nb < 0) continue;  // (not reached: meshes without wall edges)
+            const int slot = (pre.nb4.w >> (10 * al)) & 1023;
+            const int ar = nb & 3;
+            const double4 er = pre.er[al];
+            const Geo grd = make_geo(er.x, er.y, er.z, er.w);
+            const GeoR<Real> gr(grd);
+            const Real wsum = (Real)(1.0 / (gd.A + grd.A));
+            // |Gamma| n, outward: the edge vector v_{al+1} - v_al turned clockwise
+            const double ex = al == 0 ? e.x : (al == 1 ? e.z - e.x : -e.z);
+            const double ey = al == 0 ? e.y : (al == 1 ? e.w - e.y : -e.w);
+            const Real snx = (Real)ey, sny = (Real)(-ex);
+            // jump at the edge's nodes and C times it (C couples the nodes of the edge)
+            Real delta[NE], cdv[NE];
+#pragma unroll
+            for (int mm = 0; mm < NE; ++mm)
+                delta[mm] = sd[slot * NS + edge_node_rt<P>(ar, P - mm)] - sd[t * NS + edge_node(P, al, mm)];
+#pragma unroll
+            for (int mm = 0; mm < NE; ++mm) {
+                Real cd = 0;
+#pragma unroll
+                for (int qq = 0; qq < NE; ++qq) cd = mad((Real)R.C[mm][qq], delta[qq], cd);
+                cdv[mm] = cd;
+            }
+            const Real* dso = se + t * R1S + al * 2 * NE;
+            const Real* dsn = se + slot * R1S + ar * 2 * NE;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int m = 4 * q + g;
+                if (m >= NE) continue;
+                Real cd = cdv[0];
+#pragma unroll
+                for (int mm = 1; mm < NE; ++mm) cd = m == mm ? cdv[mm] : cd;
+                const Real ds0 = dso[m], ds1 = dso[NE + m];
+                const Real dn0 = dsn[P - m], dn1 = dsn[NE + P - m];
+                const Real gsx = gg.G00 * ds0 + gg.G10 * ds1, gsy = gg.G01 * ds0 + gg.G11 * ds1;
+                const Real gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
+                const Real hx = (gg.A * gsx + gr.A * gnx + Real(3) * snx * cd) * wsum;
+                const Real hy = (gg.A * gsy + gr.A * gny + Real(3) * sny * cd) * wsum;
+                const Real dx = hx - gsx, dy = hy - gsy;
+                z[q][al * 3 + 0] = snx * hx + sny * hy;
+                z[q][al * 3 + 1] = -gg.A * (gg.G00 * dx + gg.G01 * dy);
+                z[q][al * 3 + 2] = -gg.A * (gg.G10 * dx + gg.G11 * dy);
+            }
+        }
     }
-    const Real* zt = sz + t * KE;
-    const Real* dt = sd + t * N;
+    // ---- G2: rows of (K d)_t.  (The table address is laundered through an empty asm so the
+    // compiler cannot hoist these loads to the top of the tile loop, where they would hold
+    // registers through G1.)
+    const MxTab<P>* tab2 = F.tab;
+    __asm__ volatile("" : "+s"(tab2));
+    MxFrag2<P, Real> F2;
+    F2.load(tab2, lane);
+    const Real* dt = sd + t * NS;
     if constexpr (sizeof(Real) == 8) {
         d4v acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ks = 0; ks < D::KSE; ++ks) {
-            const int kk = 4 * ks + g;
-            const double b = kk < KE ? (double)zt[kk] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(F.a2[ks], b, acc, 0, 0, 0);
-        }
+        for (int ks = 0; ks < D::KSE; ++ks)  // ks = (al * 3 + s) * NQ + q
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(F2.a2[ks], (double)z[ks % NQ][ks / NQ], acc, 0, 0, 0);
 #pragma unroll
         for (int kv = 0; kv < D::KSV; ++kv) {
             const int c = kv / D::KS1;                 // volume component (compile time)
             const int l = 4 * (kv - c * D::KS1) + g;
             const double b = l < N ? (double)(cf[c] * dt[l]) : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(F.a2[D::KSE + kv], b, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(F2.a2[D::KSE + kv], b, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) y[j] = (Real)acc[j];
     } else {
         f4v hi = {0, 0, 0, 0}, lo = {0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < D::KSE32; ++ks) {
+        for (int ks = 0; ks < D::KSE32; ++ks) {  // ks = 2 q + h: elements e <-> al * 3 + s = 8 h + e
             float bv[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int kk = 32 * ks + 8 * g + e;
-                bv[e] = kk < KE ? (float)zt[kk] : 0.0f;
+                const int c = 8 * (ks & 1) + e;
+                bv[e] = c < 9 ? (float)z[ks >> 1][c < 9 ? c : 0] : 0.0f;
             }
-            bf3_mma(F.a2[ks], bv, hi, lo);
+            bf3_mma(F2.a2[ks], bv, hi, lo);
         }
 #pragma unroll
         for (int kv = 0; kv < D::KSV32; ++kv) {
@@ -289,7 +366,7 @@ __device__ __forceinline__ void mx_tile_op(const Ops& R, const MxFrag<P, Real>& 
                 const int l = 8 * (g & 1) + e;
                 bv[e] = (c < 3 && l < N) ? (float)(cc * dt[l]) : 0.0f;
             }
-            bf3_mma(F.a2[D::KSE32 + kv], bv, hi, lo);
+        bf3_mma(F2.a2[D::KSE32 + kv], bv, hi, lo);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) y[j] = (Real)(hi[j] + lo[j]);
@@ -298,9 +375,10 @@ __device__ __forceinline__ void mx_tile_op(const Ops& R, const MxFrag<P, Real>& 
 
 // Standalone apply in internal order: out = scale * K p (tiles of 64, one tile per block).
 template <int P, typename Real, class Ops>
-__global__ __launch_bounds__(kMxThreads) void k_apply_mx(const Ops* __restrict__ ops,
+__global__ __launch_bounds__(kMxThreads, 3) void k_apply_mx(const Ops* __restrict__ ops,
                                                          const MxTab<P>* __restrict__ tab,
                                                          const double4* __restrict__ geo,
+                                                         const double4* __restrict__ geo_nb,
                                                          const int4* __restrict__ nbr,
                                                          const int* __restrict__ halo_pad, int hmax,
                                                          int64_t ne, const Real* __restrict__ p,
@@ -309,22 +387,24 @@ __global__ __launch_bounds__(kMxThreads) void k_apply_mx(const Ops* __restrict__
     constexpr int N = D::N;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Real* sd = reinterpret_cast<Real*>(lds_raw);
-    Real* se = sd + (size_t)(T + hmax) * N + (size_t)T * N;
-    Real* sz = se + (size_t)(T + hmax) * D::R1;
+    Real* se = sd + (size_t)(T + hmax) * D::NS + (size_t)T * D::NS;
     const int hs = hmax > 0 ? hmax : 1;
     MxFrag<P, Real> F;
     F.load(tab, threadIdx.x & 63);
     const int64_t tile = blockIdx.x;
     const int64_t i0 = tile * T;
     const int nown = (int)((ne - i0) < T ? (ne - i0) : T) * N;
-    for (int f = threadIdx.x; f < T * N; f += kMxThreads) sd[f] = f < nown ? p[i0 * N + f] : Real(0);
+    MxPre pre;
+    mx_prefetch(geo, geo_nb, nbr, i0, ne, pre);
+    for (int f = threadIdx.x; f < T * N; f += kMxThreads)
+        sd[(f / N) * D::NS + f % N] = f < nown ? p[i0 * N + f] : Real(0);
     for (int e = threadIdx.x; e < hmax * N; e += kMxThreads) {
         const int h = halo_pad[tile * hs + e / N];
-        sd[T * N + e] = h >= 0 ? p[(int64_t)h * N + (e - (e / N) * N)] : Real(0);
+        sd[(T + e / N) * D::NS + e % N] = h >= 0 ? p[(int64_t)h * N + e % N] : Real(0);
     }
     __syncthreads();
     Real y[4];
-    mx_tile_op<P, Real, Ops>(*ops, F, geo, nbr, halo_pad + tile * hs, hmax, i0, ne, sd, se, sz, y);
+    mx_tile_op<P, Real, Ops>(*ops, F, pre, halo_pad + tile * hs, hmax, i0, ne, sd, se, y);
     const int lane = threadIdx.x & 63;
     const int t = 16 * (threadIdx.x >> 6) + (lane & 15), g = lane >> 4;
     const int64_t i = i0 + t;
@@ -341,9 +421,10 @@ __global__ __launch_bounds__(kMxThreads) void k_apply_mx(const Ops* __restrict__
 // several tiles per block, in the per-XCD chunk order; x is the FP64 correction e (or the FP32
 // correction of the mixed form).  kStream: x read and written non-temporally.
 template <int P, typename Real, class Ops, bool kStream>
-__global__ __launch_bounds__(kMxThreads) void k_cg_step_mx(const Ops* __restrict__ ops,
+__global__ __launch_bounds__(kMxThreads, SLD_MX_WAVES) void k_cg_step_mx(const Ops* __restrict__ ops,
                                                            const MxTab<P>* __restrict__ tab,
                                                            const double4* __restrict__ geo,
+                                                           const double4* __restrict__ geo_nb,
                                                            const int4* __restrict__ nbr,
                                                            const int* __restrict__ halo_pad,
                                                            int hmax, int64_t ne,
@@ -363,9 +444,9 @@ __global__ __launch_bounds__(kMxThreads) void k_cg_step_mx(const Ops* __restrict
     constexpr int NT = kMxThreads;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Real* sd = reinterpret_cast<Real*>(lds_raw);
-    Real* sr = sd + (size_t)(T + hmax) * N;
-    Real* se = sr + (size_t)T * N;
-    Real* sz = se + (size_t)(T + hmax) * D::R1;
+    constexpr int NS = D::NS;
+    Real* sr = sd + (size_t)(T + hmax) * NS;
+    Real* se = sr + (size_t)T * NS;
     const int G = gridDim.x;
     const int hs = hmax > 0 ? hmax : 1;
     const int nhe = hmax * N;
@@ -411,60 +492,103 @@ __global__ __launch_bounds__(kMxThreads) void k_cg_step_mx(const Ops* __restrict
     F.load(tab, threadIdx.x & 63);
     const Real ra = (Real)alpha, rb = (Real)beta;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // The tile loop is software-pipelined: the state of tile k + 1 (own entries and halo) is
+    // requested right after tile k's state update, so it is in flight while tile k runs G1, the
+    // edge-node stage and G2; the halo ids run one more tile ahead.
+    // Own entry f = threadIdx.x + u NT (u < PER) and halo entry e = threadIdx.x + u NT
+    // (u < kHaloPer) of a tile; hid: the entry's triangle id, -1 padding, -2 none.
+    constexpr int PER = (T * N + NT - 1) / NT;
+    Real sx[PER], srr[PER], sq[PER], sdd[PER];     // next tile: x, r, q, d of its own entries
+    Real hd[kHaloPer], hq[kHaloPer], hr[kHaloPer];  // next tile: its halo's d, q, r
+    int hid_n[kHaloPer], hid_nn[kHaloPer];         // halo ids of the next tile / the one after
+    auto load_ids = [&](int64_t tile, int (&h)[kHaloPer]) {
+#pragma unroll
+        for (int u = 0; u < kHaloPer; ++u) {
+            const int e = threadIdx.x + u * NT;
+            h[u] = (tile < t_end && e < nhe) ? halo_pad[tile * hs + e / N] : -2;
+        }
+    };
+    auto request = [&](int64_t tile) {  // state of `tile` (halo ids in hid_n)
+        const int64_t i0 = tile * T;
+        const int nown = tile < t_end ? (int)((ne - i0) < T ? (ne - i0) : T) * N : 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int f = threadIdx.x + u * NT;
+            if (f < nown) {
+                const int64_t o = i0 * N + f;
+                sdd[u] = d_in[o];
+                sq[u] = q_in[o];
+                srr[u] = r_in[o];
+                if constexpr (kStream) sx[u] = __builtin_nontemporal_load(&x[o]);
+                else sx[u] = x[o];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kHaloPer; ++u) {
+            if (hid_n[u] >= 0) {
+                const int e = threadIdx.x + u * NT;
+                const int64_t o = (int64_t)hid_n[u] * N + e % N;
+                hd[u] = d_in[o];
+                hq[u] = q_in[o];
+                hr[u] = r_in[o];
+            }
+        }
+    };
+    load_ids(t_begin, hid_n);
+    request(t_begin);
+    load_ids(t_begin + 1, hid_nn);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4;
     const int tq = 16 * wave + (lane & 15);
     for (int64_t tile = t_begin; tile < t_end; ++tile) {
         const int64_t i0 = tile * T;
         const int nown = (int)((ne - i0) < T ? (ne - i0) : T) * N;
         const int64_t base = i0 * N;
+        MxPre pre;
+        mx_prefetch(geo, geo_nb, nbr, i0, ne, pre);
         // phase 1: the tile's state update (coalesced) and the directions of tile and halo
-        for (int f = threadIdx.x; f < T * N; f += NT) {
+        // into LDS, from the registers requested one tile earlier
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int f = threadIdx.x + u * NT;
             if (f < nown) {
                 const int64_t o = base + f;
-                const Real dprev = d_in[o];
-                const Real rk = mad(-ra, q_in[o], r_in[o]);
-                const Real dk = mad(rb, dprev, rk);
-                if constexpr (kStream)
-                    __builtin_nontemporal_store(mad(ra, dprev, __builtin_nontemporal_load(&x[o])), &x[o]);
-                else
-                    x[o] = mad(ra, dprev, x[o]);
+                const Real rk = mad(-ra, sq[u], srr[u]);
+                const Real dk = mad(rb, sdd[u], rk);
+                const Real xk = mad(ra, sdd[u], sx[u]);
+                if constexpr (kStream) __builtin_nontemporal_store(xk, &x[o]);
+                else x[o] = xk;
                 r_out[o] = rk;
                 d_out[o] = dk;
-                sd[f] = dk;
-                sr[f] = rk;
+                sd[(f / N) * NS + f % N] = dk;
+                sr[(f / N) * NS + f % N] = rk;
                 acc[0] = fma((double)rk, (double)rk, acc[0]);
-            } else {
-                sd[f] = Real(0);
-                sr[f] = Real(0);
+            } else if (f < T * N) {
+                sd[(f / N) * NS + f % N] = Real(0);
+                sr[(f / N) * NS + f % N] = Real(0);
             }
         }
-        for (int e0 = threadIdx.x; e0 < nhe; e0 += 2 * NT) {
-            int id2[2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = e0 + u * NT;
-                id2[u] = e < nhe ? halo_pad[tile * hs + e / N] : -2;
-            }
-            Real hd[2], hq[2], hr[2];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (id2[u] >= 0) {
-                    const int e = e0 + u * NT;
-                    const int64_t o = (int64_t)id2[u] * N + (e - (e / N) * N);
-                    hd[u] = d_in[o];
-                    hq[u] = q_in[o];
-                    hr[u] = r_in[o];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (id2[u] >= 0) sd[T * N + e0 + u * NT] = mad(rb, hd[u], mad(-ra, hq[u], hr[u]));
-                else if (id2[u] == -1) sd[T * N + e0 + u * NT] = Real(0);  // padding
+        for (int u = 0; u < kHaloPer; ++u) {
+            const int e = threadIdx.x + u * NT;
+            if (hid_n[u] != -2) {
+                Real* dst = sd + (T + e / N) * NS + e % N;
+                *dst = hid_n[u] >= 0 ? mad(rb, hd[u], mad(-ra, hq[u], hr[u])) : Real(0);  // -1: padding
             }
         }
+        // (halo entries beyond kHaloPer per thread: very large halos only)
+        for (int e = threadIdx.x + kHaloPer * NT; e < nhe; e += NT) {
+            const int h = halo_pad[tile * hs + e / N];
+            const int64_t o = (int64_t)h * N + e % N;
+            sd[(T + e / N) * NS + e % N] = h >= 0 ? mad(rb, d_in[o], mad(-ra, q_in[o], r_in[o])) : Real(0);
+        }
+        // the next tile's state goes out now; the halo ids one tile further
+#pragma unroll
+        for (int u = 0; u < kHaloPer; ++u) hid_n[u] = hid_nn[u];
+        request(tile + 1);
+        load_ids(tile + 2, hid_nn);
         __syncthreads();
         Real y[4];
-        mx_tile_op<P, Real, Ops>(*ops, F, geo, nbr, halo_pad + tile * hs, hmax, i0, ne, sd, se, sz, y);
+        mx_tile_op<P, Real, Ops>(*ops, F, pre, halo_pad + tile * hs, hmax, i0, ne, sd, se, y);
         // phase 3: q_k = -K d_k from the output registers, and the dot products
         const int64_t i = i0 + tq;
         if (i < ne) {
@@ -474,7 +598,7 @@ __global__ __launch_bounds__(kMxThreads) void k_cg_step_mx(const Ops* __restrict
                 if (k < N) {
                     const Real qk = -y[j];
                     q_out[i * N + k] = qk;
-                    const double dk = sd[tq * N + k], rk = sr[tq * N + k], qd = qk;
+                    const double dk = sd[tq * NS + k], rk = sr[tq * NS + k], qd = qk;
                     acc[1] = fma(dk, qd, acc[1]);
                     acc[2] = fma(rk, qd, acc[2]);
                     acc[3] = fma(qd, qd, acc[3]);
@@ -561,32 +685,29 @@ const RefOps32<P>* ops32x_of(const sld_disc_s* d) {
 template <int P>
 int build_mxtab(const void* refops, MxTab<P>* out) {
     using D = MxDims<P>;
-    constexpr int N = D::N, NE = D::NE, R1 = D::R1, KE = D::KE;
+    constexpr int N = D::N, NE = D::NE, R1 = D::R1;
     const RefOps<P>& R = *static_cast<const RefOps<P>*>(refops);
-    // dense E1 [R1][N] and W2 [N][K2] in the logical layouts of mx.h
+    // E1 [R1][N]: rows (al, c, m) -> (al * 2 + c) * NE + m
     std::vector<double> E1((size_t)R1 * N, 0.0);
     for (int al = 0; al < 3; ++al)
         for (int c = 0; c < 2; ++c)
             for (int m = 0; m < NE; ++m)
                 for (int l = 0; l < N; ++l) E1[(size_t)((al * 2 + c) * NE + m) * N + l] = R.E[al][c][m][l];
-    // G2 columns: F64 layout (volume component stride NV) and BF3 layout (stride 16, edge part
-    // padded to whole k-steps of 32)
-    auto w2 = [&](int k, int kk, int vstride, int vbase) -> double {
-        if (k >= N) return 0.0;
-        if (kk < KE) {
-            const int al = kk / (3 * NE), s = (kk - al * 3 * NE) / NE, m = kk - al * 3 * NE - s * NE;
-            if (s == 0) {
-                // line term: row edge_node(al, mm) takes M1[mm][m] tn_m
-                for (int mm = 0; mm < NE; ++mm)
-                    if (edge_node(P, al, mm) == k) return R.M1[mm][m];
-                return 0.0;
-            }
-            return R.Pt[al][s - 1][k][m];
+    // entry (row k, edge al, quantity s, edge node m) of W2's edge part: s = 0 the normal flux
+    // of node m, which enters the line term on the edge's nodes (row edge_node(al, mm) takes
+    // M1[mm][m]); s = 1, 2 the correction's reference components (Pt)
+    auto w2e = [&](int k, int al, int s, int m) -> double {
+        if (k >= N || m >= NE) return 0.0;
+        if (s == 0) {
+            for (int mm = 0; mm < NE; ++mm)
+                if (edge_node(P, al, mm) == k) return R.M1[mm][m];
+            return 0.0;
         }
-        if (kk < vbase) return 0.0;
-        const int c = (kk - vbase) / vstride, l = (kk - vbase) - c * vstride;
-        if (c >= 3 || l >= N) return 0.0;
-        return R.S[c][k][l];
+        return R.Pt[al][s - 1][k][m];
+    };
+    // entry (row k, component c, node l) of the volume part
+    auto w2v = [&](int k, int c, int l) -> double {
+        return (k < N && c < 3 && l < N) ? R.S[c][k][l] : 0.0;
     };
     for (int rb = 0; rb < 2; ++rb)
         for (int ks = 0; ks < D::KS1; ++ks)
@@ -594,9 +715,19 @@ int build_mxtab(const void* refops, MxTab<P>* out) {
                 const int row = 16 * rb + (lane & 15), col = 4 * ks + (lane >> 4);
                 out->a1[rb][ks][lane] = (row < R1 && col < N) ? E1[(size_t)row * N + col] : 0.0;
             }
-    for (int ks = 0; ks < D::KS2; ++ks)
-        for (int lane = 0; lane < 64; ++lane)
-            out->a2[ks][lane] = w2(lane & 15, 4 * ks + (lane >> 4), D::NV, 4 * D::KSE);
+    // F64 G2: edge k-step (al * 3 + s) * NQ + q holds node m = g + 4 q in lane group g; volume
+    // k-step KSE + c * KS1 + u holds node l = 4 u + g of component c
+    for (int lane = 0; lane < 64; ++lane) {
+        const int k = lane & 15, g = lane >> 4;
+        for (int ks = 0; ks < D::KSE; ++ks) {
+            const int c9 = ks / D::NQ, q = ks % D::NQ;
+            out->a2[ks][lane] = w2e(k, c9 / 3, c9 % 3, 4 * q + g);
+        }
+        for (int kv = 0; kv < D::KSV; ++kv) {
+            const int c = kv / D::KS1, u = kv % D::KS1;
+            out->a2[D::KSE + kv][lane] = w2v(k, c, 4 * u + g);
+        }
+    }
     for (int rb = 0; rb < 2; ++rb)
         for (int lane = 0; lane < 64; ++lane)
             for (int e = 0; e < 8; ++e) {
@@ -605,13 +736,25 @@ int build_mxtab(const void* refops, MxTab<P>* out) {
                 split3_host((row < R1 && col < N) ? E1[(size_t)row * N + col] : 0.0, sp);
                 for (int s = 0; s < 3; ++s) out->b1[rb][s][lane][e] = sp[s];
             }
-    for (int ks = 0; ks < D::KS232; ++ks)
-        for (int lane = 0; lane < 64; ++lane)
-            for (int e = 0; e < 8; ++e) {
+    // BF3 G2: edge k-step 2 q + h, element e of lane group g: (al * 3 + s) = 8 h + e at node
+    // m = g + 4 q; volume k-step KSE32 + kv, element e of lane group g: component 2 kv + g / 2,
+    // node 8 (g % 2) + e
+    for (int lane = 0; lane < 64; ++lane) {
+        const int k = lane & 15, g = lane >> 4;
+        for (int e = 0; e < 8; ++e) {
+            for (int ks = 0; ks < D::KSE32; ++ks) {
+                const int q = ks >> 1, c9 = 8 * (ks & 1) + e;
                 uint16_t sp[3];
-                split3_host(w2(lane & 15, 32 * ks + 8 * (lane >> 4) + e, 16, 32 * D::KSE32), sp);
+                split3_host(c9 < 9 ? w2e(k, c9 / 3, c9 % 3, 4 * q + g) : 0.0, sp);
                 for (int s = 0; s < 3; ++s) out->b2[ks][s][lane][e] = sp[s];
             }
+            for (int kv = 0; kv < D::KSV32; ++kv) {
+                uint16_t sp[3];
+                split3_host(w2v(k, 2 * kv + (g >> 1), 8 * (g & 1) + e), sp);
+                for (int s = 0; s < 3; ++s) out->b2[D::KSE32 + kv][s][lane][e] = sp[s];
+            }
+        }
+    }
     return 0;
 }
 
@@ -662,8 +805,8 @@ hipError_t launch_apply_mx(const sld_disc_s* d, const void* p, void* out, bool f
                            m->perm, static_cast<const float*>(p), w.d32[1]);
         SLD_MX_DISPATCH(d->p, hipLaunchKernelGGL((k_apply_mx<PP, float, RefOps32<PP>>), dim3(tiles),
                                                  dim3(kMxThreads), lds, s, ops32x_of<PP>(d), tab_of<PP>(d),
-                                                 m->geo_i, m->nbr_i, m->halo_pad, m->hmax, m->ne,
-                                                 w.d32[1], w.q32[1]));
+                                                 m->geo_i, m->geo_nb, m->nbr_i, m->halo_pad, m->hmax,
+                                                 m->ne, w.d32[1], w.q32[1]));
         hipLaunchKernelGGL(k_scatter_mx<float>, dim3(w.grid), dim3(kBlockFlat), 0, s, n, d->nphi,
                            m->perm, w.q32[1], static_cast<float*>(out));
     } else {
@@ -671,8 +814,8 @@ hipError_t launch_apply_mx(const sld_disc_s* d, const void* p, void* out, bool f
                            m->perm, static_cast<const double*>(p), w.d[1]);
         SLD_MX_DISPATCH(d->p, hipLaunchKernelGGL((k_apply_mx<PP, double, RefOps<PP>>), dim3(tiles),
                                                  dim3(kMxThreads), lds, s, ops64_of<PP>(d), tab_of<PP>(d),
-                                                 m->geo_i, m->nbr_i, m->halo_pad, m->hmax, m->ne,
-                                                 w.d[1], w.q[1]));
+                                                 m->geo_i, m->geo_nb, m->nbr_i, m->halo_pad, m->hmax,
+                                                 m->ne, w.d[1], w.q[1]));
         hipLaunchKernelGGL(k_scatter_mx<double>, dim3(w.grid), dim3(kBlockFlat), 0, s, n, d->nphi,
                            m->perm, w.q[1], static_cast<double*>(out));
     }
@@ -691,7 +834,8 @@ hipError_t launch_cg_step_mx(const sld_disc_s* d, int parity, bool f32, bool str
     SLD_MX_DISPATCH(d->p, hipLaunchKernelGGL((k_cg_step_mx<PP, R, OPS<PP>, ST>), dim3(G),          \
                                              dim3(kMxThreads), lds, s,                              \
                                              reinterpret_cast<const OPS<PP>*>(f32 ? d->ops32_dev : d->ops_dev), \
-                                             tab_of<PP>(d), m->geo_i, m->nbr_i, m->halo_pad,        \
+                                             tab_of<PP>(d), m->geo_i, m->geo_nb, m->nbr_i,          \
+                                             m->halo_pad,                                           \
                                              m->hmax, m->ne, X, RB[parity], QB[parity], DB[parity], \
                                              RB[o], QB[o], DB[o], PART + parity * 4 * G,            \
                                              PART + o * 4 * G, SC, parity))

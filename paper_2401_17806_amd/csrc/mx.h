@@ -8,10 +8,10 @@
 //       E1 [6 NE x N] * [d_t ...]            rows (alpha, c, m) -> (alpha * 2 + c) * NE + m,
 //   G2: the rows of (K d)_t from the per-triangle quantities z_t formed between the two,
 //       W2 [N x K2] * [z_t ...],
-//       z = (per edge alpha: the normal flux n.x_H at the edge nodes, -A (G Delta)_0,
+//       z = (per edge alpha and edge node: the normal flux n.x_H, -A (G Delta)_0,
 //            -A (G Delta)_1), then -A m00 d, -A m01 d, -A m11 d (volume term)
 //       W2 = (per edge alpha: M1 placed on the edge's nodes, Pt[alpha][0], Pt[alpha][1]),
-//            then S0, S1, S2.
+//            then S0, S1, S2 (the k-step order of the edge part is given in MxDims).
 // Between the two products only pointwise work per edge node remains (the closed form of
 // Mhat^{-1} on the edge nodes, which couples each edge's two sides).
 //
@@ -37,16 +37,25 @@ struct MxDims {
     static constexpr int NE = P + 1;                 // nodes on an edge
     static constexpr int R1 = 6 * NE;                // rows of G1 (<= 32: two row blocks)
     static constexpr int KE = 9 * NE;                // edge part of G2's inner dimension
-    // F64: k-steps of 4
+    // the nodes of an edge are dealt to the four lane groups of a 16-triangle block: node
+    // m = g + 4 q to lane group g (q < NQ)
+    static constexpr int NQ = (NE + 3) / 4;
+    // F64: k-steps of 4; the edge part of G2 takes k-step (al * 3 + s) * NQ + q at node
+    // m = g + 4 q (s: 0 the normal flux, 1 and 2 the two reference components of the correction)
     static constexpr int KS1 = (N + 3) / 4;
-    static constexpr int KSE = (KE + 3) / 4;
+    static constexpr int KSE = 9 * NQ;
     static constexpr int NV = KS1 * 4;               // stride of one volume component
     static constexpr int KSV = 3 * KS1;
     static constexpr int KS2 = KSE + KSV;
-    // BF3: k-steps of 32 (G1 needs one: N <= 15 < 32)
-    static constexpr int KSE32 = (KE + 31) / 32;
+    // BF3: k-steps of 32 (G1 needs one: N <= 15 < 32); the edge part of G2 takes k-step
+    // 2 q + h, element e of lane group g being (al * 3 + s) = 8 h + e at node m = g + 4 q
+    static constexpr int KSE32 = 2 * NQ;
     static constexpr int KSV32 = 2;                  // three volume components of 16
     static constexpr int KS232 = KSE32 + KSV32;
+    // LDS row strides (words) of the per-triangle arrays: odd, so that lanes reading the same
+    // entry of consecutive triangles fall in different banks
+    static constexpr int NS = N | 1;
+    static constexpr int R1S = R1 | 1;
 };
 
 // A operands of both engines, in lane order (each lane loads its own entries).

@@ -144,6 +144,11 @@ struct CgScalars {
 constexpr double kReplaceFactor = 1e-3;
 constexpr double kGapRestart = 0.3;
 int cg_grid_for(const sld_disc_s* d, bool* front);
+// engine 0 of sld_cg_solve (the library's choice): whether the pressure iterations of each
+// precision run on the matrix cores, by the measured time per iteration on the 512x512x2, p = 3
+// mesh (the vector-unit kernels are faster there in both precisions)
+constexpr bool kAutoMx64 = false;
+constexpr bool kAutoMx32 = false;
 // sigma > 0: the viscous system (sigma Mbar - K) x = -b instead of -K x = -b (no 1^perp
 // projection, no gauge)
 hipError_t launch_cg_setup(const sld_disc_s* d, const double* b, const double* p0, bool warm,

@@ -64,7 +64,8 @@ def traffic(fetch_db: str, write_db: str, workload: str, copy_bytes: int) -> Non
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     h = hashlib.sha256()
-    for name in ("kernels_cg.hip", "device_common.h", "refops.h", "sld_internal.h"):
+    for name in ("kernels_cg.hip", "kernels_mx.hip", "mx.h", "device_common.h", "refops.h",
+                 "sld_internal.h"):
         with open(os.path.join(root, "csrc", name), "rb") as f:
             h.update(f.read())
     f_cg = counter_means(fetch_db, "k_cg_step")
