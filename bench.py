@@ -162,13 +162,20 @@ def cpu_baseline(wl, workload, lattice_mesh, random_fourier_field, iters=100, sa
     _, infon = solve.cg(K, b, tol=1e-30, maxit=iters, matvec=solve.row_block_matvec(K, cores))
     rate1 = ne * nphi * info1["iters"] / info1["seconds"]
     raten = ne * nphi * infon["iters"] / infon["seconds"]
-    return {"value": raten, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+    legs = {"one_thread": {"value": rate1, "cores": 1,
+                           "ms_per_iter": 1e3 * info1["seconds"] / max(info1["iters"], 1)},
+            "all_cores": {"value": raten, "cores": cores,
+                          "ms_per_iter": 1e3 * infon["seconds"] / max(infon["iters"], 1)}}
+    # the faster of the two is the baseline (on a loaded or throttled host the split product
+    # can lose to one thread); both are reported
+    best = "all_cores" if raten > rate1 else "one_thread"
+    return {"value": legs[best]["value"], "unit": "DOF-updates/s", "cores": legs[best]["cores"],
+            "kind": "oracle",
             "sample": f"{iters} CG iterations of the oracle's assembled-CSR CG on the "
                       f"{n}x{n}x2 p={wl['p']} mesh of the workload's family ({ne * nphi} DOFs; "
-                      f"assembly {t_asm:.1f} s excluded), sparse product on {cores} cores",
-            "ms_per_iter": 1e3 * infon["seconds"] / max(infon["iters"], 1),
-            "one_thread": {"value": rate1, "cores": 1,
-                           "ms_per_iter": 1e3 * info1["seconds"] / max(info1["iters"], 1)},
+                      f"assembly {t_asm:.1f} s excluded); timed with the sparse product on one "
+                      f"thread and split over {cores} cores, the faster reported",
+            "ms_per_iter": legs[best]["ms_per_iter"], **legs,
             "seconds": info1["seconds"] + infon["seconds"] + t_asm}
 
 

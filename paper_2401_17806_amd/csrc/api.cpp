@@ -937,7 +937,24 @@ hipError_t capture_block(sld_disc_s* d, bool fp32, bool shift, int gb, hipGraphE
     return e;
 }
 
-// SLD_CG_TRACE=1 in the environment: each FP64 residual replacement is printed to stderr
+// Relative gap between the refreshed and the recursive FP32 residual beyond which a reliable
+// update restarts the FP32 Krylov process instead of keeping its search direction.
+#ifndef SLD_REL_GAP_MAX
+#define SLD_REL_GAP_MAX 0.3
+#endif
+// FP32 iterations after which a reliable update is made even if the FP32 residual has not
+// dropped by the refresh factor.  The residual norm of CG on this system is far from monotone
+// (on the 512x512x2, p = 3 solve it first grows twelvefold and stays above its start for about
+// 4000 iterations), and over such a stretch the FP32 recursion drifts: without this bound the
+// first update found a 95% gap and restarted the process, and the mixed solve took 23483 FP32
+// iterations instead of 19491 (FP64 CG: 17765).  An update costs one FP64 residual evaluation,
+// under 0.3% of the iterations between two updates.
+#ifndef SLD_REL_MAX_SPAN
+#define SLD_REL_MAX_SPAN 512
+#endif
+
+// SLD_CG_TRACE=1 in the environment: each FP64 residual replacement and each reliable update of
+// the mixed form is printed to stderr
 bool cg_trace() {
     static const bool on = [] {
         const char* v = std::getenv("SLD_CG_TRACE");
@@ -1257,7 +1274,9 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
         // while the recursive FP32 residual still tracks the true one (relative gap <= kGapMax);
         // beyond that the kept direction is no longer conjugate to the new residual and the
         // FP32 process restarts from it.
-        constexpr double kGapMax = 0.3;
+        constexpr double kGapMax = SLD_REL_GAP_MAX;
+        constexpr int kMaxSpan = SLD_REL_MAX_SPAN;
+        int last_update = 0;
         const double refresh = prm->inner_rtol;
         int total = 0, base = 0;
         SLD_HIP_CHECK(launch_rel_init(d, prm->rtol, prm->maxit, s));
@@ -1271,8 +1290,10 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
                 if (in.done || base + in.iters >= prm->maxit) break;
                 // (the block's graph ended with the peek: RRNOW is current)
                 if (w.host_scal_in[S::RRNOW] <= refresh * refresh * rr_ref) break;
+                if (base + in.iters - last_update >= kMaxSpan) break;
             }
             total = base + in.iters;
+            last_update = total;
             SLD_HIP_CHECK(launch_rel_update(d, s));
             SLD_HIP_CHECK(launch_rel_peek(d, 0, s));
             SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
@@ -1307,6 +1328,13 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
                 prev64 = rr;
                 restart = true;
             }
+            if (cg_trace())
+                std::fprintf(stderr,
+                             "sld cg: reliable update %d after %d FP32 iterations: FP64 residual "
+                             "%.3e, gap %.3e of the FP32 one%s%s\n",
+                             outer, total, bb > 0 ? std::sqrt(rr / bb) : 0.0,
+                             rr_ref > 0 ? std::sqrt(w.host_scal_in[S::GAP] / rr_ref) : 0.0,
+                             in.done ? ", FP32 process at rtol" : "", restart ? ", restart" : "");
             if (restart) {
                 base = total;
                 SLD_HIP_CHECK(launch_rel_restart(d, s));

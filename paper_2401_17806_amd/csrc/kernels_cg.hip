@@ -158,6 +158,25 @@ __device__ __forceinline__ void sum_dot_partials(const double* __restrict__ part
     block_sum_all<4, NT>(v);
 }
 
+// Centring of the FP32 operator inputs.  Every piece of K that one lane or wave evaluates -- the
+// volume term and the coupling through one edge -- maps constants to zero: the reference
+// stiffness and edge-derivative rows sum to zero and the jump of a constant vanishes (the
+// pressure operator's wall pieces give back a sub-triangle stiffness share, which does the
+// same).  So the piece may subtract any one value c from all the DOFs it reads, its own and the
+// neighbour's, without changing its result in exact arithmetic.  In FP32 it changes a lot: for
+// the smooth modes that CG resolves last, the DOFs a piece reads agree to many digits, the
+// reference contractions cancel them, and the rounding of those sums (relative to |p|, not to
+// the differences) swamps the small result.  With c = the triangle's first DOF the sums see
+// only the local variation.  Measured on the 512x512x2, p = 3 Taylor-Green pressure solve: the
+// mixed form's FP32 iterations fall from 28758 to 19491 (FP64 CG: 17765), the same count as with
+// the operator evaluated in FP64 arithmetic on FP32 vectors.  The FP64 kernel is left as it is.
+// v -= c on every entry
+template <typename Real, int N>
+__device__ __forceinline__ void centre(Real (&v)[N], Real c) {
+#pragma unroll
+    for (int l = 0; l < N; ++l) v[l] -= c;
+}
+
 // Dynamic LDS of k_cg_step, in words of the arithmetic type: sd [(T + hmax) N] directions d_k
 // of the tile then of its halo; sr [T N] residuals r_k of the tile; sm [T][R][N] partial rows
 // (R = 4 roles in the one-tile-per-block variant, 3 lanes otherwise).
@@ -196,6 +215,8 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
     constexpr int R = kFront ? 4 : 3;                  // partial rows per triangle
     constexpr int PER = (T * N + NT - 1) / NT;  // tile entries per thread
     constexpr int HB = 4;                                     // halo entries per thread and batch
+    // FP32 operator inputs centred per piece (see centre above)
+    constexpr bool kCentre = sizeof(Real) == 4 && !kShift;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Real* sd = reinterpret_cast<Real*>(lds_raw);
     Real* sr = sd + (size_t)(T + hmax) * N;
@@ -388,8 +409,10 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
                 Real pl[N], y[N];
 #pragma unroll
                 for (int l = 0; l < N; ++l) pl[l] = sd[lane * N + l];
+                [[maybe_unused]] const Real c = pl[0];
                 const double4 e = geo[i];
                 if (role == 3) {
+                    if constexpr (kCentre) centre(pl, c);
                     volume_wave_core<P, Ops, Real>(*ops, e, pl, y);
                     if constexpr (kShift) {
                         const double sa = -scal[S::SIGMA] * (e.x * e.w - e.y * e.z);
@@ -410,10 +433,12 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
                         ar = nb & 3;
 #pragma unroll
                         for (int l = 0; l < N; ++l) pr[l] = sd[slot * N + rot_sel<P>(ar, l)];
+                        if constexpr (kCentre) centre(pr, c);
                     } else {
 #pragma unroll
                         for (int l = 0; l < N; ++l) pr[l] = Real(0);
                     }
+                    if constexpr (kCentre) centre(pl, c);
                     const int wk = wall_kind(kShift, wall_i, i, role);
                     if (role == 0) edge_wave_core<P, 0, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y, wk);
                     else if (role == 1) edge_wave_core<P, 1, Ops, Real>(*ops, e, nb, ar, er, pl, pr, y, wk);
@@ -440,6 +465,7 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
                     ar = nb & 3;
 #pragma unroll
                     for (int l = 0; l < N; ++l) pr[l] = sd[slot * N + rot_sel<P>(ar, l)];
+                    if constexpr (kCentre) centre(pr, pl[0]);
                     // (the bandwidth-bound several-tiles variant reads the neighbour's geometry
                     // through its id: the per-edge copy in geo_nb measured 3% slower here)
                     er = geo[nb >> 2];
@@ -447,6 +473,7 @@ __global__ __launch_bounds__(kFront ? kBlockCG : kBlockTri) void k_cg_step(const
 #pragma unroll
                     for (int l = 0; l < N; ++l) pr[l] = Real(0);
                 }
+                if constexpr (kCentre) centre(pl, pl[0]);
                 const double4 ei = geo[i];
                 edge_lane_core<P, Ops, Real>(al, *ops, ei, nb, ar, er, pl, pr, y,
                                              wall_kind(kShift, wall_i, i, al));
