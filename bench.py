@@ -244,7 +244,7 @@ def bench_sl_advect(args, torch, sld, lattice_mesh, random_fourier_field, nc=3):
         "config": {"workload": f"{args.workload}: sl_advect of {nc} fields, CFL 0.5, "
                                f"{ne} triangles, p={p}", "triangles": ne, "p": p, "fields": nc},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved is not None else None, "traffic": None,
                      "kernel": f"k_sl_advect<{p}>", "kernel_us": kernel_us,
                      "kernel_us_source": "HIP events around the launches on the launch stream",
                      "bytes_per_launch": sbytes},
@@ -324,7 +324,7 @@ def bench_imex(args, torch, sld, lattice_mesh):
     timed = sum(r["pressure"]["timed_iters"] for r in reps)
     step_us = sum(r["pressure"]["step_us"] * r["pressure"]["timed_iters"] for r in reps) / max(timed, 1)
     sbytes = alg_bytes_per_tri(nphi) * ne
-    achieved = sbytes / (step_us * 1e-6) / 1e9
+    achieved = sbytes / (step_us * 1e-6) / 1e9 if step_us > 0 else None
     res = {
         "metric": "SL-IMEX (R = 0) Taylor-Green steps/s",
         "value": steps / elapsed, "unit": "steps/s", "n_gpus": 1, "steps": steps,
@@ -341,7 +341,7 @@ def bench_imex(args, torch, sld, lattice_mesh):
         "velocity_rel_rms_error_vs_vortex": err, "t_end": t_end,
         "divergence_norm_at_end": divfree,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+                     "frac": achieved / HBM_PEAK_GBS if achieved is not None else None,
                      "traffic": measured_traffic(args.workload),
                      "kernel": f"k_cg_step<{p}, double> (pressure CG iteration)",
                      "kernel_us_source": "HIP events around captured blocks of iterations",
@@ -423,7 +423,7 @@ def bench_cavity(args, torch, sld, lattice_mesh):
         "max_velocity": float(v.abs().max()), "temperature_range": [float(T.min()), float(T.max())],
         "divergence_norm_at_end": float(torch.linalg.norm(disc.sld_divergence(v))),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved is not None else None, "traffic": None,
                      "kernel": f"k_cg_step<{p}, {'double' if word == 8 else 'float'}> (pressure CG iteration)",
                      "kernel_us_source": "pressure solve wall time / iterations",
                      "kernel_us": step_us, "bytes_per_launch": sbytes},
@@ -553,10 +553,12 @@ def main():
     # graph_block iterations (the production path), blocks whose launches all iterated
     timed = sum(r["timed_iters"] for r in reps)
     word = 4 if mixed else 8
-    if not mixed:
-        step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / max(timed, 1)
+    by_events = not mixed and timed > 0
+    if by_events:
+        step_us = sum(r["step_us"] * r["timed_iters"] for r in reps) / timed
     else:
-        # FP32 inner iterations: solve wall time (refreshes included) per inner iteration
+        # FP32 inner iterations, or solves too short for a whole captured block: solve wall
+        # time (refreshes and replacements included) per iteration
         step_us = 1e6 * sum(r["seconds"] for r in reps) / max(iters, 1)
     abytes = alg_bytes_per_tri(nphi, word) * ne
     kbytes = step_bytes_per_tri(nphi, word) * ne
@@ -565,8 +567,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": None if mixed else measured_traffic(args.workload),
                 "kernel": f"k_cg_step<{p}, {'float' if mixed else 'double'}> (one fused CG iteration)",
-                "kernel_us_source": ("solve wall time / inner iterations" if mixed else
-                                     "HIP events around captured blocks of iterations"),
+                "kernel_us_source": ("HIP events around captured blocks of iterations"
+                                     if by_events else "solve wall time / iterations"),
                 "kernel_us": step_us,
                 "bytes_per_launch": abytes,
                 "bytes_per_tri": alg_bytes_per_tri(nphi, word),

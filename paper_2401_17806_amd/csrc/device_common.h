@@ -116,6 +116,92 @@ __device__ __forceinline__ void relabel(double4 e, int ar, double& e1x, double& 
 __device__ __forceinline__ double mad(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float mad(float a, float b, float c) { return fmaf(a, b, c); }
 
+// The reference matrices are uniform across a wave, so they are read with scalar loads into
+// SGPRs and used as FMA operands.  Left alone, the compiler issues the scalar loads of a whole
+// contraction stage (or, in a loop over tiles, of all stages) far ahead of their use; at p = 3
+// that is hundreds of SGPRs, which it spills into VGPR lanes and reads back one v_readlane at a
+// time (about 600 extra vector instructions per wave and tile).  fence_ref hands back the same
+// reference through an empty asm statement that takes `dep`, a result of the previous small
+// contraction, as input: the loads of the next one cannot be issued before that result exists,
+// so only one contraction's matrices (at most 20 doubles) are live at a time.  The arithmetic
+// is unchanged.  Measured on the 512x512x2, p = 3 CG iteration: 121.5 -> 112.6 us (FP64) and
+// 78.0 -> 72.4 us (FP32); 128x128x2, p = 3: 11.29 -> 10.43 us.  At p = 2 and 4 the ordering
+// cost more than it saved (the p = 2 cavity mesh 20.9 -> 21.9 us, 256x256x2 at p = 4 56.1 ->
+// 61.6 us), so only p = 3 takes the fenced forms below.
+template <class T, typename D>
+__device__ __forceinline__ const T& fence_ref(const T& r, const D& dep) {
+    int z = 0;
+    __asm__ volatile("" : "+s"(z) : "v"(dep));
+    return *(&r + z);
+}
+
+// s_d = sum_l M(d, l) v_l for d = 0, 1, 2, with M(d, l) = mat(R, d, l) (one row of each of three
+// reference matrices); at p = 3 one fenced contraction per matrix, dep the previous result
+template <int P, class Ops, typename Real, int N, class F, typename D>
+__device__ __forceinline__ void contract3(const Ops& R, F mat, const Real (&v)[N], Real& s0,
+                                          Real& s1, Real& s2, const D& dep) {
+    s0 = s1 = s2 = Real(0);
+    if constexpr (P == 3) {
+        const Ops& R0 = fence_ref(R, dep);
+#pragma unroll
+        for (int l = 0; l < N; ++l) s0 = mad(mat(R0, 0, l), v[l], s0);
+        const Ops& R1 = fence_ref(R, s0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) s1 = mad(mat(R1, 1, l), v[l], s1);
+        const Ops& R2 = fence_ref(R, s1);
+#pragma unroll
+        for (int l = 0; l < N; ++l) s2 = mad(mat(R2, 2, l), v[l], s2);
+    } else {
+        (void)dep;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            s0 = mad(mat(R, 0, l), v[l], s0);
+            s1 = mad(mat(R, 1, l), v[l], s1);
+            s2 = mad(mat(R, 2, l), v[l], s2);
+        }
+    }
+}
+
+// the reference for the next contraction: fenced on dep at p = 3, R itself otherwise
+template <int P, class Ops, typename D>
+__device__ __forceinline__ const Ops& next_ref(const Ops& R, const D& dep) {
+    if constexpr (P == 3) return fence_ref(R, dep);
+    (void)dep;
+    return R;
+}
+
+// Edge-node derivatives of both sides at edge node m: ds = E[as][.][m] pl (this side, local
+// edge as), dn = E[0][.][P - m] pr (the neighbour, relabelled so the edge is its edge 0)
+template <int P, class Ops, typename Real, int N, typename D>
+__device__ __forceinline__ void edge_derivs(const Ops& R, int as, int m, const Real (&pl)[N],
+                                            const Real (&pr)[N], Real& ds0, Real& ds1,
+                                            Real& dn0, Real& dn1, const D& dep) {
+    ds0 = ds1 = dn0 = dn1 = Real(0);
+    if constexpr (P == 3) {
+        const Ops& Rm = fence_ref(R, dep);
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            ds0 = mad(Rm.E[as][0][m][l], pl[l], ds0);
+            ds1 = mad(Rm.E[as][1][m][l], pl[l], ds1);
+        }
+        const Ops& Rn = fence_ref(R, ds1);
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            dn0 = mad(Rn.E[0][0][P - m][l], pr[l], dn0);
+            dn1 = mad(Rn.E[0][1][P - m][l], pr[l], dn1);
+        }
+    } else {
+        (void)dep;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            ds0 = mad(R.E[as][0][m][l], pl[l], ds0);
+            ds1 = mad(R.E[as][1][m][l], pl[l], ds1);
+            dn0 = mad(R.E[0][0][P - m][l], pr[l], dn0);
+            dn1 = mad(R.E[0][1][P - m][l], pr[l], dn1);
+        }
+    }
+}
+
 // geometric factors rounded to the arithmetic type
 template <typename Real>
 struct GeoR {
@@ -161,24 +247,16 @@ __device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, 
 #pragma unroll
     for (int q = 0; q < T.nrep; ++q) {
         const int k = T.rep[q];
-        Real s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            s0 = mad(R.S[0][k][l], pl[l], s0);
-            s1 = mad(R.S[1][k][l], pl[l], s1);
-            s2 = mad(R.S[2][k][l], pl[l], s2);
-        }
+        Real s0, s1, s2;
+        contract3<P>(R, [&](const Ops& Q, int d, int l) { return Q.S[d][k][l]; }, pl, s0, s1, s2,
+                     q > 0 ? y[T.rep[q > 0 ? q - 1 : 0]] : pl[0]);
         y[k] = -g.A * (m00 * s0 + m01 * s1 + m11 * s2);
     }
     if (T.centre >= 0 && al == 0) {
         const int k = T.centre >= 0 ? T.centre : 0;
-        Real s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            s0 = mad(R.S[0][k][l], pl[l], s0);
-            s1 = mad(R.S[1][k][l], pl[l], s1);
-            s2 = mad(R.S[2][k][l], pl[l], s2);
-        }
+        Real s0, s1, s2;
+        contract3<P>(R, [&](const Ops& Q, int d, int l) { return Q.S[d][k][l]; }, pl, s0, s1, s2,
+                     y[T.rep[T.nrep - 1]]);
         y[k] = -g.A * (m00 * s0 + m01 * s1 + m11 * s2);
     }
     const Real snx = (Real)e1y, sny = (Real)(-e1x);  // |Gamma| n, outward, of local edge 0
@@ -211,19 +289,14 @@ __device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, 
     Real gd0[NE], gd1[NE], tn[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-        Real ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            ds0 = mad(R.E[0][0][m][l], pl[l], ds0);
-            ds1 = mad(R.E[0][1][m][l], pl[l], ds1);
-            dn0 = mad(R.E[0][0][P - m][l], pr[l], dn0);
-            dn1 = mad(R.E[0][1][P - m][l], pr[l], dn1);
-        }
+        Real ds0, ds1, dn0, dn1;
+        edge_derivs<P>(R, 0, m, pl, pr, ds0, ds1, dn0, dn1, m > 0 ? gd1[m > 0 ? m - 1 : 0] : delta[0]);
+        const Ops& Rc = next_ref<P>(R, dn1);
         const Real gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
         const Real gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
         Real cd = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) cd = mad(R.C[m][q], delta[q], cd);
+        for (int q = 0; q < NE; ++q) cd = mad(Rc.C[m][q], delta[q], cd);
         const Real hx = (g.A * gsx + gr.A * gnx + Real(3) * snx * cd) * wsum;
         const Real hy = (g.A * gsy + gr.A * gny + Real(3) * sny * cd) * wsum;
         tn[m] = snx * hx + sny * hy;
@@ -234,19 +307,21 @@ __device__ __forceinline__ void edge_lane_core(int al, const Ops& R, double4 e, 
     // line term |Gamma| int phi_k n.x_H on the edge nodes
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
+        const Ops& Rm = next_ref<P>(R, m > 0 ? y[m > 0 ? m - 1 : 0] : tn[NE - 1]);
         Real s = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) s = mad(R.M1[m][q], tn[q], s);
+        for (int q = 0; q < NE; ++q) s = mad(Rm.M1[m][q], tn[q], s);
         y[m] += s;
     }
     // sub-triangle correction -A sum_d Pt_d (G Delta)_d
 #pragma unroll
     for (int k = 0; k < N; ++k) {
+        const Ops& Rk = next_ref<P>(R, k > 0 ? y[k > 0 ? k - 1 : 0] : gd1[NE - 1]);
         Real s = 0;
 #pragma unroll
         for (int m = 0; m < NE; ++m) {
-            s = mad(R.Pt[0][0][k][m], gd0[m], s);
-            s = mad(R.Pt[0][1][k][m], gd1[m], s);
+            s = mad(Rk.Pt[0][0][k][m], gd0[m], s);
+            s = mad(Rk.Pt[0][1][k][m], gd1[m], s);
         }
         y[k] = mad(-g.A, s, y[k]);
     }
@@ -271,13 +346,9 @@ __device__ __forceinline__ void volume_wave_core(const Ops& R, double4 e,
     const Real m11 = (Real)(gd.G10 * gd.G10 + gd.G11 * gd.G11);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        Real s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            s0 = mad(R.S[0][k][l], pl[l], s0);
-            s1 = mad(R.S[1][k][l], pl[l], s1);
-            s2 = mad(R.S[2][k][l], pl[l], s2);
-        }
+        Real s0, s1, s2;
+        contract3<P>(R, [&](const Ops& Q, int d, int l) { return Q.S[d][k][l]; }, pl, s0, s1, s2,
+                     k > 0 ? y[k > 0 ? k - 1 : 0] : pl[0]);
         y[k] = -A * (m00 * s0 + m01 * s1 + m11 * s2);
     }
 }
@@ -305,13 +376,9 @@ __device__ __forceinline__ void edge_wave_core(const Ops& R, double4 e, int nb, 
         const Real m11 = (Real)(gd.G10 * gd.G10 + gd.G11 * gd.G11);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            Real s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-            for (int l = 0; l < N; ++l) {
-                s0 = mad(R.Sh[AL][0][k][l], pl[l], s0);
-                s1 = mad(R.Sh[AL][1][k][l], pl[l], s1);
-                s2 = mad(R.Sh[AL][2][k][l], pl[l], s2);
-            }
+            Real s0, s1, s2;
+            contract3<P>(R, [&](const Ops& Q, int d, int l) { return Q.Sh[AL][d][k][l]; }, pl, s0,
+                         s1, s2, k > 0 ? y[k > 0 ? k - 1 : 0] : pl[0]);
             y[k] = g.A * (m00 * s0 + m01 * s1 + m11 * s2);
         }
         return;
@@ -333,19 +400,14 @@ __device__ __forceinline__ void edge_wave_core(const Ops& R, double4 e, int nb, 
     Real gd0[NE], gd1[NE], tn[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-        Real ds0 = 0, ds1 = 0, dn0 = 0, dn1 = 0;
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            ds0 = mad(R.E[AL][0][m][l], pl[l], ds0);
-            ds1 = mad(R.E[AL][1][m][l], pl[l], ds1);
-            dn0 = mad(R.E[0][0][P - m][l], pr[l], dn0);
-            dn1 = mad(R.E[0][1][P - m][l], pr[l], dn1);
-        }
+        Real ds0, ds1, dn0, dn1;
+        edge_derivs<P>(R, AL, m, pl, pr, ds0, ds1, dn0, dn1, m > 0 ? gd1[m > 0 ? m - 1 : 0] : delta[0]);
+        const Ops& Rc = next_ref<P>(R, dn1);
         const Real gsx = g.G00 * ds0 + g.G10 * ds1, gsy = g.G01 * ds0 + g.G11 * ds1;
         const Real gnx = gr.G00 * dn0 + gr.G10 * dn1, gny = gr.G01 * dn0 + gr.G11 * dn1;
         Real cd = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) cd = mad(R.C[m][q], delta[q], cd);
+        for (int q = 0; q < NE; ++q) cd = mad(Rc.C[m][q], delta[q], cd);
         const Real hx = (g.A * gsx + gr.A * gnx + Real(3) * snx * cd) * wsum;
         const Real hy = (g.A * gsy + gr.A * gny + Real(3) * sny * cd) * wsum;
         tn[m] = snx * hx + sny * hy;
@@ -356,19 +418,21 @@ __device__ __forceinline__ void edge_wave_core(const Ops& R, double4 e, int nb, 
     // line term |Gamma| int phi_k n.x_H on the edge nodes
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
+        const Ops& Rm = next_ref<P>(R, m > 0 ? y[edge_node(P, AL, m > 0 ? m - 1 : 0)] : tn[NE - 1]);
         Real s = 0;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) s = mad(R.M1[m][q], tn[q], s);
+        for (int q = 0; q < NE; ++q) s = mad(Rm.M1[m][q], tn[q], s);
         y[edge_node(P, AL, m)] = s;
     }
     // sub-triangle correction -A sum_d Pt_d (G Delta)_d
 #pragma unroll
     for (int k = 0; k < N; ++k) {
+        const Ops& Rk = next_ref<P>(R, k > 0 ? y[k > 0 ? k - 1 : 0] : gd1[NE - 1]);
         Real s = 0;
 #pragma unroll
         for (int m = 0; m < NE; ++m) {
-            s = mad(R.Pt[AL][0][k][m], gd0[m], s);
-            s = mad(R.Pt[AL][1][k][m], gd1[m], s);
+            s = mad(Rk.Pt[AL][0][k][m], gd0[m], s);
+            s = mad(Rk.Pt[AL][1][k][m], gd1[m], s);
         }
         y[k] = mad(-g.A, s, y[k]);
     }
