@@ -615,6 +615,12 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         if (cap > 0 && cap < G) G = (cap + 7) & ~7;
     }
     w.grid = G;
+    w.grid32 = cg_grid32_for(d, G, w.front);
+    if (const char* g32 = std::getenv("SLD_CG_GRID32")) {  // debugging aid: FP32 grid
+        const int v = std::atoi(g32);
+        if (v >= G) w.grid32 = (v + 7) & ~7;
+    }
+    const int GP = std::max(G, w.grid32);  // partial sums laid out by either grid
     if (const char* sx = std::getenv("SLD_CG_STREAM_X"))  // debugging aid: force x streaming
         w.stream_x = std::atoi(sx) != 0 ? 1 : 0;
     std::lock_guard<std::mutex> lk(device_setup_mutex());
@@ -647,7 +653,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
     }
     if (e == hipSuccess) e = dalloc(&w.b, nv);
     if (e == hipSuccess) e = dalloc(&w.part, size_t(8) * G);
-    if (e == hipSuccess) e = dalloc(&w.part_s, size_t(2) * G);
+    if (e == hipSuccess) e = dalloc(&w.part_s, size_t(2) * GP);
     if (e == hipSuccess) e = dalloc(&w.scal, CgScalars::NSCAL);
     if (e == hipSuccess) e = dalloc(&w.wall_i, size_t(m->ne));
     for (int k = 0; k < 2; ++k) {
@@ -656,7 +662,7 @@ sld_status sld_disc_create(sld_mesh m, int32_t p, uint32_t flags, sld_disc* out)
         if (e == hipSuccess) e = dalloc(&w.d32[k], nv);
     }
     if (e == hipSuccess) e = dalloc(&w.e32, nv);
-    if (e == hipSuccess) e = dalloc(&w.part32, size_t(8) * G);
+    if (e == hipSuccess) e = dalloc(&w.part32, size_t(8) * GP);
     if (e == hipSuccess) e = dalloc(&w.scal_in, CgScalars::NSCAL);
     if (e == hipSuccess) {
         up.copy(d->ops_dev, d->ops_host, d->ops_bytes);
@@ -1170,6 +1176,7 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
         sw.scal = q;
         sw.host_scal = dw.host_scal;
         sw.grid = dw.grid;
+        sw.grid32 = dw.grid32;
         sw.front = dw.front;
         sw.stream_x = dw.stream_x;
         sw.wall_i = dw.wall_i;

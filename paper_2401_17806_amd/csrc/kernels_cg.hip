@@ -28,6 +28,10 @@ namespace {
 
 typedef CgScalars S;
 
+// blocks of the FP32 iteration and of the kernels that write or read its dot partials (the MFMA
+// form runs on the FP64 grid)
+inline int rel_grid(const CgWork& w) { return w.use_mx ? w.grid : w.grid32; }
+
 // row k of Mref v
 template <int P>
 __device__ __forceinline__ double mass_row(const RefOps<P>& R, int k,
@@ -1044,6 +1048,31 @@ int cg_grid_for(const sld_disc_s* d, bool* front) {
     return (int)((g + 7) & ~int64_t(7));
 }
 
+// Grid of the FP32 three-lane iteration.  It holds fewer registers than the FP64 kernel, so
+// more of its blocks stay resident; when its working set is well beyond the cache-resident
+// range (above 64 MiB: five vectors and the geometry) the grid is all of them.  Measured per
+// FP32 iteration, p = 3: 512x512x2 (130 MB) 74.6 us at the FP64 grid of 1024 blocks, 72.1 us
+// at 1536, 79.4 us at 2048; 256x256x2 (33 MB) 26.0 us at 1024, 27.3 us at 1536.  The
+// one-tile-per-block variant keeps the FP64 grid.
+int cg_grid32_for(const sld_disc_s* d, int grid, bool front) {
+    const sld_mesh_s* m = d->mesh;
+    if (front) return grid;
+    if ((int64_t)5 * m->ne * d->nphi * 4 + m->ne * 48 <= (int64_t(64) << 20)) return grid;
+    const int64_t tiles = (m->ne + kTriPerBlock - 1) / kTriPerBlock;
+    int per = 0, cus = 0;
+    const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(float), false);
+    hipError_t e = hipSuccess;
+    SLD_DISPATCH(d->p, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &per, (k_cg_step<PP, float, RefOps32<PP>, false, false, false>), kBlockTri,
+                           lds));
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device);
+    if (e != hipSuccess || per <= 0 || cus <= 0) return grid;
+    int64_t g = std::min<int64_t>(tiles, (int64_t)per * cus);
+    g = std::min<int64_t>(g, kCgMaxGrid);
+    g = (g + 7) & ~int64_t(7);
+    return g > grid ? (int)g : grid;
+}
+
 hipError_t launch_wall_mask(const sld_disc_s* d, const unsigned char* edge_mask, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     hipLaunchKernelGGL(k_wall_mask, dim3((unsigned)((m->ne + kBlockFlat - 1) / kBlockFlat)),
@@ -1074,7 +1103,7 @@ hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hi
 hipError_t launch_cg_step32(const sld_disc_s* d, int parity, hipStream_t s) {
     const sld_mesh_s* m = d->mesh;
     const CgWork& w = d->cg;
-    const int G = w.grid;
+    const int G = rel_grid(w);
     const int o = 1 - parity;
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
@@ -1106,7 +1135,7 @@ hipError_t launch_rel_init(const sld_disc_s* d, double rtol, int maxit, hipStrea
     const CgWork& w = d->cg;
     const int64_t n = d->mesh->ne * d->nphi;
     hipLaunchKernelGGL(k_rel_init, dim3(1), dim3(kBlockFlat), 0, s, w.scal, w.scal_in, rtol, maxit);
-    hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
+    hipLaunchKernelGGL(k_rel_to32, dim3(rel_grid(w)), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
                        w.q32[0], w.d32[0], w.e32, 1, w.part32, w.part_s);
     return hipGetLastError();
 }
@@ -1124,9 +1153,9 @@ hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s) {
                                           w.r[0], w.part_s, w.scal, 0.0, w.wall_i, 0));
     hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal,
                        (int)S::RR, 1.0);
-    hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
+    hipLaunchKernelGGL(k_rel_to32, dim3(rel_grid(w)), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
                        w.q32[0], w.d32[0], w.e32, 0, w.part32, w.part_s);
-    hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal_in,
+    hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, rel_grid(w), w.scal_in,
                        (int)S::GAP, 1.0);
     return hipGetLastError();
 }
@@ -1136,7 +1165,7 @@ hipError_t launch_rel_update(const sld_disc_s* d, hipStream_t s) {
 hipError_t launch_rel_restart(const sld_disc_s* d, hipStream_t s) {
     const CgWork& w = d->cg;
     const int64_t n = d->mesh->ne * d->nphi;
-    hipLaunchKernelGGL(k_rel_to32, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
+    hipLaunchKernelGGL(k_rel_to32, dim3(rel_grid(w)), dim3(kBlockFlat), 0, s, n, w.r[0], w.scal, w.r32[0],
                        w.q32[0], w.d32[0], w.e32, 1, w.part32, w.part_s);
     hipLaunchKernelGGL(k_rel_restart, dim3(1), dim3(64), 0, s, w.scal_in);
     return hipGetLastError();
@@ -1144,7 +1173,7 @@ hipError_t launch_rel_restart(const sld_disc_s* d, hipStream_t s) {
 
 hipError_t launch_rel_peek(const sld_disc_s* d, int resume, hipStream_t s) {
     const CgWork& w = d->cg;
-    hipLaunchKernelGGL(k_rel_peek, dim3(1), dim3(kBlockFlat), 0, s, w.part32, w.grid, w.scal_in,
+    hipLaunchKernelGGL(k_rel_peek, dim3(1), dim3(kBlockFlat), 0, s, w.part32, rel_grid(w), w.scal_in,
                        resume);
     return hipGetLastError();
 }

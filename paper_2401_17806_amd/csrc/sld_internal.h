@@ -75,7 +75,9 @@ struct CgWork {
     double* part_s = nullptr;      // [2][grid] partials of setup / finish reductions
     double* scal = nullptr;        // device scalars (CgScalars)
     double* host_scal = nullptr;   // pinned mirror of scal, then two block copy slots
-    int grid = 0;                  // blocks of every CG kernel
+    int grid = 0;                  // blocks of every CG kernel (FP64)
+    int grid32 = 0;                // blocks of the FP32 vector-unit iteration and its reliable
+                                   // updates (>= grid: that kernel holds fewer registers)
     bool front = false;            // iteration kernel variant: one tile per block, four roles
     int stream_x = -1;             // x with non-temporal accesses: -1 by working-set size, 0/1
     unsigned char* wall_i = nullptr;  // [ne] internal order: Dirichlet wall edges (bit per local
@@ -144,6 +146,7 @@ struct CgScalars {
 constexpr double kReplaceFactor = 1e-3;
 constexpr double kGapRestart = 0.3;
 int cg_grid_for(const sld_disc_s* d, bool* front);
+int cg_grid32_for(const sld_disc_s* d, int grid, bool front);
 // engine 0 of sld_cg_solve (the library's choice): whether the pressure iterations of each
 // precision run on the matrix cores, by the measured time per iteration on the 512x512x2, p = 3
 // mesh (the vector-unit kernels are faster there in both precisions)
