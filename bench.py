@@ -455,6 +455,9 @@ def main():
     ap.add_argument("--engine", choices=("auto", "valu", "mfma"), default="auto",
                     help="reference contractions of the pressure iterations: the library's "
                          "choice, the vector units, or the matrix cores")
+    ap.add_argument("--algorithm", choices=("auto", "classic", "pipelined"), default="auto",
+                    help="FP64 pressure iterations: the library's choice, CG, or pipelined CG "
+                         "(meshes of one tile per block)")
     ap.add_argument("--inner-rtol", type=float, default=0.5,
                     help="mixed: residual reduction of the FP32 process between FP64 refreshes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -525,7 +528,8 @@ def main():
         disc.sld_pressure_rhs(vstar, 1.0 / coef, out=b)
         _, rep = disc.sld_cg_solve(b, p=pres, rtol=args.rtol, graph_block=args.graph_block,
                                    profile=profile and precision == "fp64", precision=precision,
-                                   inner_rtol=args.inner_rtol, maxit=200000, engine=args.engine)
+                                   inner_rtol=args.inner_rtol, maxit=200000, engine=args.engine,
+                                   algorithm=args.algorithm if precision == "fp64" else "auto")
         disc.sld_velocity_correct(vstar, pres, coef, out=vnew)
         return rep
 

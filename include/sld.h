@@ -229,6 +229,13 @@ typedef struct {
                              meshes without wall edges, the vector units otherwise; 0 = the
                              library's choice per precision (the faster form measured on the
                              512x512x2, p = 3 mesh).  Viscous solves use the vector units. */
+    int32_t pipelined;    /* FP64 pressure iterations: 1 = CG as in Section 3.3; 2 = pipelined
+                             CG (Ghysels and Vanroose: the same iterates in exact arithmetic,
+                             the operator applied to a vector the previous iteration completed,
+                             so it overlaps the global dot-product sums; residual replacement
+                             as for CG), only where the CG grid holds one tile of 64 triangles
+                             per block (cache-resident meshes, e.g. 128x128x2) and with the
+                             vector units, SLD_E_INVALID otherwise; 0 = the library's choice. */
 } sld_cg_params;
 
 typedef struct {

@@ -233,7 +233,7 @@ extern "C" {
 
 const char* sld_last_error(void) { return g_err.c_str(); }
 
-int32_t sld_abi_version(void) { return 2; }
+int32_t sld_abi_version(void) { return 3; }
 
 sld_status sld_mesh_create(const double* xy, int64_t nv, const int32_t* tri, int64_t ne,
                            const double* period, int32_t device, sld_mesh* out) {
@@ -996,10 +996,12 @@ sld_status run_iterations(sld_disc_s* d, bool fp32, bool shift, int gb, bool pro
         for (auto& e : w.events) SLD_HIP_CHECK(hipEventCreate(&e));
     }
     bool& gmx = w.graph_mx[fp32 ? 2 : (shift ? 1 : 0)];
-    if (graph == nullptr || graph_block != gb || gmx != w.use_mx) {
+    const bool pcg_key = !fp32 && !shift && w.graph_pcg != w.use_pcg;
+    if (graph == nullptr || graph_block != gb || gmx != w.use_mx || pcg_key) {
         SLD_HIP_CHECK(capture_block(d, fp32, shift, gb, &graph));
         graph_block = gb;
         gmx = w.use_mx;
+        if (!fp32 && !shift) w.graph_pcg = w.use_pcg;
     }
     const int kind = shift ? 1 : 0;
     int expect = 0;  // fewest blocks among the recorded solves (0: none recorded)
@@ -1188,7 +1190,16 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
                 "sld_cg_solve: engine must be 0 (library's choice), 1 (vector units) or 2 "
                 "(matrix cores)");
     w.use_mx = w.mx_ok && (prm->engine == 2 || (prm->engine == 0 && (mixed ? kAutoMx32 : kAutoMx64)));
+    SLD_REQUIRE(prm->pipelined >= 0 && prm->pipelined <= 2, SLD_E_INVALID,
+                "sld_cg_solve: pipelined must be 0 (library's choice), 1 (classic CG) or 2 "
+                "(pipelined CG)");
+    const bool pcg_ok = !mixed && !shift && ws == nullptr && !w.use_mx && pcg_possible(d);
+    SLD_REQUIRE(prm->pipelined != 2 || pcg_ok, SLD_E_INVALID,
+                "sld_cg_solve: pipelined CG serves FP64 pressure solves with the vector units on "
+                "meshes whose CG grid holds one tile per block");
+    w.use_pcg = pcg_ok && (prm->pipelined == 2 || (prm->pipelined == 0 && kAutoPcg));
     SLD_HIP_CHECK(launch_cg_setup(d, b, p, prm->warm_start != 0, prm->rtol, prm->maxit, sigma, s));
+    if (w.use_pcg) SLD_HIP_CHECK(launch_pcg_init(d, s));
     IterStats st;
     // status: 1 converged, 2 no convergence (maxit, or the FP64 floor), 3 breakdown
     int outer = 0, status = 0;
@@ -1227,7 +1238,7 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
             }
             const int src = (seg_iters + 1 - seg0) & 1;
             const double rr_rec = rr;
-            SLD_HIP_CHECK(launch_cg_replace(d, src, sigma, s));
+            SLD_HIP_CHECK(w.use_pcg ? launch_pcg_replace(d, s) : launch_cg_replace(d, src, sigma, s));
             SLD_HIP_CHECK(hipMemcpyAsync(w.host_scal, w.scal, S::NSCAL * sizeof(double),
                                          hipMemcpyDeviceToHost, s));
             SLD_HIP_CHECK(hipStreamSynchronize(s));

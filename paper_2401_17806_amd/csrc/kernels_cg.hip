@@ -870,6 +870,342 @@ __global__ __launch_bounds__(kBlockFlat) void k_rep_scal(const double* __restric
     }
 }
 
+// ---------------------------------------------------------------- pipelined CG
+// Ghysels and Vanroose's pipelined CG on A = -K (or its FP64 residual-replacement form), for
+// meshes whose tiles each fit one block.  With gamma_i = r_i.r_i and delta_i = w_i.r_i, w_i = A r_i:
+//   q_i = A w_i
+//   beta_i = gamma_i / gamma_{i-1},  alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
+//   (first iteration: beta = 0, alpha = gamma / delta)
+//   z_i = q_i + beta z_{i-1},  s_i = w_i + beta s_{i-1},  p_i = r_i + beta p_{i-1}
+//   x += alpha p_i,  r_{i+1} = r_i - alpha s_i,  w_{i+1} = w_i - alpha z_i.
+// In exact arithmetic the iterates are those of CG (Section 3.3).  The operator is applied to
+// w_i, which the previous launch completed, so a launch evaluates it while the previous
+// launch's partial sums of gamma and delta are still arriving; CG proper cannot start its
+// operator before those sums give it alpha and beta.  Only w is read across tiles (the halo),
+// so only w is double-buffered by parity; r, z, s, p and the correction e are updated in place.
+// Scalars: alpha_i and gamma_i by parity in PA0 / PG0 (+1), like the iteration counter.
+
+template <int P>
+__global__ __launch_bounds__(kBlockCG) void k_pcg_step(const RefOps<P>* __restrict__ ops,
+                                                       const double4* __restrict__ geo,
+                                                       const double4* __restrict__ geo_nb,
+                                                       const int4* __restrict__ nbr,
+                                                       const int* __restrict__ halo_pad, int hmax,
+                                                       int64_t ne, double* __restrict__ e,
+                                                       double* __restrict__ r,
+                                                       double* __restrict__ z,
+                                                       double* __restrict__ sv,
+                                                       double* __restrict__ pv,
+                                                       const double* __restrict__ w_in,
+                                                       double* __restrict__ w_out,
+                                                       const double* __restrict__ part_in,
+                                                       double* __restrict__ part_out,
+                                                       double* __restrict__ scal, int parity) {
+    constexpr int N = RefOps<P>::NPHI;
+    constexpr int T = kTriPerBlock;
+    constexpr int NT = kBlockCG;
+    constexpr int PER = (T * N + NT - 1) / NT;  // tile entries per thread
+    constexpr int HB = 4;                       // halo entries per thread and batch
+    constexpr int PB = 4;                       // partials per thread requested at entry
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double* sw = reinterpret_cast<double*>(lds_raw);  // [(T + hmax) N]: w of the tile, then halo
+    double* sm = sw + (size_t)(T + hmax) * N;          // [T][4][N]: rows of K w by role
+    const int G = gridDim.x;
+    const int hs = hmax > 0 ? hmax : 1;
+    const int nhe = hmax * N;
+    // one tile per block, by the same XCD-aware map as k_cg_step (G is a multiple of 8); the
+    // blocks beyond the last tile contribute zero partials
+    const int64_t tile = (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+    const int64_t i0 = tile * T;
+    if (i0 >= ne) {
+        if (threadIdx.x == 0) {
+            part_out[blockIdx.x] = 0.0;
+            part_out[G + blockIdx.x] = 0.0;
+        }
+        return;
+    }
+    const int nown = (int)((ne - i0) < T ? (ne - i0) : T) * N;
+    // the stop flag and the iteration count, read once for the whole block (block 0 of this
+    // launch may set the flag while other blocks start)
+    __shared__ double flags[2];
+    if (threadIdx.x == 0) {
+        flags[0] = scal[S::DONE];
+        flags[1] = scal[S::ITER0 + parity];
+    }
+    __syncthreads();
+    if (flags[0] != 0.0) return;
+    const double it = flags[1];
+    // entry: the tile's w and state, the halo ids, and this thread's first partials
+    double vw[PER], vr[PER], vz[PER], vs[PER], vp[PER], ve[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int f = threadIdx.x + u * NT;
+        if (f < nown) {
+            const int64_t o = i0 * N + f;
+            vw[u] = w_in[o];
+            vr[u] = r[o];
+            vz[u] = z[o];
+            vs[u] = sv[o];
+            vp[u] = pv[o];
+            ve[u] = e[o];
+        }
+    }
+    double pg[PB], pd[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+        const int b = threadIdx.x + u * NT;
+        pg[u] = b < G ? part_in[b] : 0.0;
+        pd[u] = b < G ? part_in[G + b] : 0.0;
+    }
+    for (int e0 = 0; e0 < nhe; e0 += HB * NT) {
+        int hid[HB];
+        double hw[HB];
+#pragma unroll
+        for (int u = 0; u < HB; ++u) {
+            const int ee = e0 + threadIdx.x + u * NT;
+            hid[u] = ee < nhe ? halo_pad[tile * hs + ee / N] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < HB; ++u)
+            if (hid[u] >= 0) {
+                const int ee = e0 + threadIdx.x + u * NT;
+                hw[u] = w_in[(int64_t)hid[u] * N + (ee - (ee / N) * N)];
+            }
+#pragma unroll
+        for (int u = 0; u < HB; ++u)
+            if (hid[u] >= 0) sw[T * N + e0 + threadIdx.x + u * NT] = hw[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int f = threadIdx.x + u * NT;
+        if (f < nown) sw[f] = vw[u];
+    }
+    __syncthreads();
+    // q = A w: one wave per role (waves 0..2: local edge 0..2, wave 3: volume term), one lane
+    // per triangle, operands from LDS (the pressure operator: walls carry no dual coupling)
+    {
+        const int role = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        const int64_t i = i0 + lane;
+        if (i < ne) {
+            double pl[N], y[N];
+#pragma unroll
+            for (int l = 0; l < N; ++l) pl[l] = sw[lane * N + l];
+            const double4 eg = geo[i];
+            if (role == 3) {
+                volume_wave_core<P, RefOps<P>, double>(*ops, eg, pl, y);
+            } else {
+                const int4 nb4 = nbr[i];
+                const int nb = pick(nb4, role);
+                const int slot = (nb4.w >> (10 * role)) & 1023;
+                const double4 er = geo_nb[i * 3 + role];
+                double pr[N];
+                int ar = 0;
+                if (nb >= 0) {
+                    ar = nb & 3;
+#pragma unroll
+                    for (int l = 0; l < N; ++l) pr[l] = sw[slot * N + rot_sel<P>(ar, l)];
+                } else {
+#pragma unroll
+                    for (int l = 0; l < N; ++l) pr[l] = 0.0;
+                }
+                if (role == 0) edge_wave_core<P, 0, RefOps<P>, double>(*ops, eg, nb, ar, er, pl, pr, y);
+                else if (role == 1) edge_wave_core<P, 1, RefOps<P>, double>(*ops, eg, nb, ar, er, pl, pr, y);
+                else edge_wave_core<P, 2, RefOps<P>, double>(*ops, eg, nb, ar, er, pl, pr, y);
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) sm[(lane * 4 + role) * N + k] = y[k];
+        }
+    }
+    // gamma_i, delta_i: the previous launch's partials in a fixed order (the same in every block)
+    double v[2] = {0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+        v[0] += pg[u];
+        v[1] += pd[u];
+    }
+    for (int b = threadIdx.x + PB * NT; b < G; b += NT) {
+        v[0] += part_in[b];
+        v[1] += part_in[G + b];
+    }
+    block_sum_all<2, NT>(v);  // (its barriers also complete the operator rows in sm)
+    const double g = v[0], dl = v[1];
+    int stop = 0;
+    bool restart = false;
+    double alpha = 0.0, beta = 0.0;
+    if (!isfinite(g)) stop = S::kBreakdown;
+    else if (g <= scal[S::TOL2]) stop = S::kConverged;
+    else if (g <= scal[S::RTH] || it - scal[S::PLR] >= (double)kPcgSpan) stop = S::kRefresh;
+    else if (it > scal[S::MAXIT]) stop = S::kMaxit;
+    else if (it == 0.0) {
+        if (!(dl > 0.0) || !isfinite(dl)) stop = S::kBreakdown;
+        else alpha = g / dl;
+    } else {
+        beta = g / scal[S::PG0 + parity];
+        const double den = dl - beta * g / scal[S::PA0 + parity];
+        if (!isfinite(den)) {
+            stop = S::kBreakdown;
+        } else if (!(den > 0.0)) {
+            // the recurrences of w, z and s have drifted from A r, A s and A p: a replacement
+            // recomputes them, and the directions restart
+            stop = S::kRefresh;
+            restart = true;
+        } else {
+            alpha = g / den;
+        }
+    }
+    if (stop) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[S::DONE] = (double)stop;
+            scal[S::RR] = g;
+            scal[S::ITER] = it;  // updates that reached x
+            // the scalars this state was reached with, for a replacement that keeps it
+            scal[S::PA0] = scal[S::PA0 + parity];
+            scal[S::PG0] = scal[S::PG0 + parity];
+            if (restart) scal[S::GAP] = -1.0;  // read by k_pcg_rep_scal: restart
+        }
+        return;
+    }
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int f = threadIdx.x + u * NT;
+        if (f < nown) {
+            const int t = f / N, k = f - t * N;
+            double q = (sm[(t * 4) * N + k] + sm[(t * 4 + 1) * N + k]) + sm[(t * 4 + 2) * N + k];
+            q += sm[(t * 4 + 3) * N + k];
+            q = -q;
+            const double zz = fma(beta, vz[u], q);
+            const double ss = fma(beta, vs[u], vw[u]);
+            const double pp = fma(beta, vp[u], vr[u]);
+            const double rn = fma(-alpha, ss, vr[u]);
+            const double wn = fma(-alpha, zz, vw[u]);
+            const int64_t o = i0 * N + f;
+            __builtin_nontemporal_store(zz, &z[o]);
+            __builtin_nontemporal_store(ss, &sv[o]);
+            __builtin_nontemporal_store(pp, &pv[o]);
+            __builtin_nontemporal_store(fma(alpha, pp, ve[u]), &e[o]);
+            __builtin_nontemporal_store(rn, &r[o]);
+            __builtin_nontemporal_store(wn, &w_out[o]);
+            acc[0] = fma(rn, rn, acc[0]);
+            acc[1] = fma(wn, rn, acc[1]);
+        }
+    }
+    block_sum_all<2, NT>(acc);
+    if (threadIdx.x == 0) {
+        part_out[blockIdx.x] = acc[0];
+        part_out[G + blockIdx.x] = acc[1];
+        if (blockIdx.x == 0) {
+            scal[S::ITER0 + (1 - parity)] = it + 1.0;
+            scal[S::PA0 + (1 - parity)] = alpha;
+            scal[S::PG0 + (1 - parity)] = g;
+        }
+    }
+}
+
+// w = -Kr (Kr = K r given), partials of gamma = r.r and delta = w.r into part[0, G) and
+// part[G, 2G); zero: also z = s = p = 0 (a first iteration follows)
+__global__ __launch_bounds__(kBlockFlat) void k_pcg_dots(int64_t n, const double* __restrict__ r,
+                                                         const double* __restrict__ kr,
+                                                         double* __restrict__ w,
+                                                         double* __restrict__ z,
+                                                         double* __restrict__ sv,
+                                                         double* __restrict__ pv, int zero,
+                                                         double* __restrict__ part) {
+    double acc[2] = {0.0, 0.0};
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        const double rv = r[t], wv = -kr[t];
+        w[t] = wv;
+        if (zero) {
+            z[t] = 0.0;
+            sv[t] = 0.0;
+            pv[t] = 0.0;
+        }
+        acc[0] = fma(rv, rv, acc[0]);
+        acc[1] = fma(wv, rv, acc[1]);
+    }
+    block_sum_all<2, kBlockFlat>(acc);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc[0];
+        part[gridDim.x + blockIdx.x] = acc[1];
+    }
+}
+
+// out = -in
+__global__ __launch_bounds__(kBlockFlat) void k_pcg_neg(int64_t n, const double* __restrict__ in,
+                                                        double* __restrict__ out) {
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat)
+        out[t] = -in[t];
+}
+
+// replacement: r = rt (the recomputed residual), partials of |rt - r|^2 into gap_part
+__global__ __launch_bounds__(kBlockFlat) void k_pcg_gap(int64_t n, const double* __restrict__ rt,
+                                                        double* __restrict__ r,
+                                                        double* __restrict__ gap_part) {
+    double acc[1] = {0.0};
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        const double v = rt[t], g = v - r[t];
+        r[t] = v;
+        acc[0] = fma(g, g, acc[0]);
+    }
+    block_sum_all<1, kBlockFlat>(acc);
+    if (threadIdx.x == 0) gap_part[blockIdx.x] = acc[0];
+}
+
+// scalars after a replacement (one block): as k_rep_scal, but a restart also clears the
+// directions (k_pcg_restart_dirs reads the decision from ITER0 / ITER1)
+__global__ __launch_bounds__(kBlockFlat) void k_pcg_rep_scal(const double* __restrict__ part,
+                                                             const double* __restrict__ gap_part,
+                                                             int nb, double* __restrict__ scal,
+                                                             double factor2, double gapmax2) {
+    const double rr = reduce_partials<kBlockFlat>(part, nb);
+    const double gap = reduce_partials<kBlockFlat>(gap_part, nb);
+    if (threadIdx.x == 0) {
+        const double done_iters = scal[S::ITER];
+        const bool force = scal[S::GAP] < 0.0;  // the iteration asked for a restart
+        if (scal[S::DONE] == (double)S::kConverged && rr > scal[S::TOLU])
+            scal[S::TOL2] = 0.25 * scal[S::TOL2];
+        scal[S::RR] = rr;
+        scal[S::GAP] = gap;
+        scal[S::RTH] = factor2 * rr;
+        scal[S::DONE] = 0.0;
+        if (force || gap > gapmax2 * rr) {
+            scal[S::ITER0] = 0.0;  // a first iteration: beta = 0, z = s = p = 0
+            scal[S::ITER1] = 0.0;
+            scal[S::PLR] = 0.0;
+            scal[S::MAXIT] = scal[S::MAXIT] - done_iters;
+        } else {
+            scal[S::ITER0] = done_iters;  // the launch that stopped, run again
+            scal[S::ITER1] = done_iters;
+            scal[S::PLR] = done_iters;
+        }
+    }
+}
+
+__global__ void k_pcg_scal_init(double* __restrict__ scal) {
+    if (threadIdx.x == 0) {
+        scal[S::PLR] = 0.0;
+        scal[S::GAP] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlockFlat) void k_pcg_restart_dirs(int64_t n,
+                                                                 const double* __restrict__ scal,
+                                                                 double* __restrict__ z,
+                                                                 double* __restrict__ sv,
+                                                                 double* __restrict__ pv) {
+    if (scal[S::ITER0] != 0.0 || scal[S::ITER] == 0.0) return;
+    for (int64_t t = (int64_t)blockIdx.x * kBlockFlat + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlockFlat) {
+        z[t] = 0.0;
+        sv[t] = 0.0;
+        pv[t] = 0.0;
+    }
+}
+
 // ---------------------------------------------------------------- static CG workspace
 // The workspace of sld_cg_solve_static, for callers that cannot allocate device memory: one
 // array per device, held from the library's first use on that device until the process ends.
@@ -981,6 +1317,7 @@ hipError_t launch_cg_step(const sld_disc_s* d, int parity, bool shift, hipStream
     if (G & 7) return hipErrorInvalidValue;  // the tile-chunk map needs a multiple of 8
     const bool front = w.front && (int64_t)G * kTriPerBlock >= m->ne;
     const bool sx = stream_x_for(d, sizeof(double)) != 0;
+    if (!shift && w.use_pcg) return launch_pcg_step(d, parity, s);
     if (!shift && w.use_mx) return launch_cg_step_mx(d, parity, false, sx, s);
     const size_t lds = step_lds_bytes(d->nphi, m->hmax, sizeof(double), front);
 #define SLD_STEP64(F, SH, ST)                                                                   \
@@ -1175,5 +1512,91 @@ hipError_t launch_rel_peek(const sld_disc_s* d, int resume, hipStream_t s) {
     const CgWork& w = d->cg;
     hipLaunchKernelGGL(k_rel_peek, dim3(1), dim3(kBlockFlat), 0, s, w.part32, rel_grid(w), w.scal_in,
                        resume);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- pipelined CG launchers
+// Buffers: r = r[0], z = q[0], s = q[1], p = r[1], w = d[parity] (read) / d[1 - parity]
+// (written), the correction e; d[1] is scratch during the setup and a replacement.
+
+bool pcg_possible(const sld_disc_s* d) {
+    const CgWork& w = d->cg;
+    return w.front && w.grid > 0 && (int64_t)w.grid * kTriPerBlock >= d->mesh->ne;
+}
+
+namespace {
+// out = K v (internal order; the pressure operator)
+hipError_t apply_k(const sld_disc_s* d, const double* v, double* out, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_apply_internal<PP>,
+                                          dim3((unsigned)((m->ne + kTriPerBlock - 1) / kTriPerBlock)),
+                                          dim3(kBlockTri), 0, s, ops_of<PP>(d), m->geo_i, m->nbr_i,
+                                          m->ne, v, out, 0.0, d->cg.wall_i));
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_pcg_step(const sld_disc_s* d, int parity, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    const CgWork& w = d->cg;
+    const int G = w.grid;
+    if (!pcg_possible(d) || (G & 7)) return hipErrorInvalidValue;
+    const int o = 1 - parity;
+    const size_t lds = sizeof(double) * (size_t)d->nphi *
+                       (size_t)(kTriPerBlock + m->hmax + 4 * kTriPerBlock);
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_pcg_step<PP>, dim3(G), dim3(kBlockCG), lds, s,
+                                          ops_of<PP>(d), m->geo_i, m->geo_nb, m->nbr_i,
+                                          m->halo_pad, m->hmax, m->ne, w.e, w.r[0], w.q[0],
+                                          w.q[1], w.r[1], w.d[parity], w.d[o],
+                                          w.part + parity * 4 * G, w.part + o * 4 * G, w.scal,
+                                          parity));
+    return hipGetLastError();
+}
+
+// after launch_cg_setup (r_0 = K x - b_int in r[0]): w_0 = A r_0, z = s = p = 0, the partials of
+// gamma_0 and delta_0 where the first launch (parity 0) reads them
+hipError_t launch_pcg_init(const sld_disc_s* d, hipStream_t s) {
+    const CgWork& w = d->cg;
+    const int64_t n = d->mesh->ne * d->nphi;
+    hipError_t e = apply_k(d, w.r[0], w.d[1], s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pcg_dots, dim3(w.grid), dim3(kBlockFlat), 0, s, n, w.r[0], w.d[1], w.d[0],
+                       w.q[0], w.q[1], w.r[1], 1, w.part);
+    // first replacement once |r| has dropped by kPcgReplaceFactor (the setup left the partials of
+    // |r_0|^2 in part_s)
+    hipLaunchKernelGGL(k_scal_reduce, dim3(1), dim3(kBlockFlat), 0, s, w.part_s, w.grid, w.scal,
+                       (int)S::RTH, kPcgReplaceFactor * kPcgReplaceFactor);
+    hipLaunchKernelGGL(k_pcg_scal_init, dim3(1), dim3(64), 0, s, w.scal);
+    return hipGetLastError();
+}
+
+// Residual replacement: x += e, e = 0; r = K x - b_int recomputed (|r - r_recursive|^2 -> GAP);
+// w = A r, s = A p, z = A s recomputed so that the recurrences hold again; gamma, delta summed;
+// the scalars as after a classic replacement, a restart also clearing z, s and p
+hipError_t launch_pcg_replace(const sld_disc_s* d, hipStream_t s) {
+    const sld_mesh_s* m = d->mesh;
+    const CgWork& w = d->cg;
+    const int G = w.grid;
+    const int64_t n = m->ne * d->nphi;
+    double* tmp = w.d[1];
+    hipLaunchKernelGGL(k_cg_fold, dim3(G), dim3(kBlockFlat), 0, s, n, w.x, w.e);
+    SLD_DISPATCH(d->p, hipLaunchKernelGGL(k_cg_resid<PP>, dim3(G), dim3(kBlockTri), 0, s,
+                                          ops_of<PP>(d), m->geo_i, m->nbr_i, m->ne, w.x, w.b, tmp,
+                                          w.part_s, w.scal, 0.0, w.wall_i, 1));
+    hipLaunchKernelGGL(k_pcg_gap, dim3(G), dim3(kBlockFlat), 0, s, n, tmp, w.r[0], w.part_s + G);
+    hipError_t e = apply_k(d, w.r[1], tmp, s);  // K p
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pcg_neg, dim3(G), dim3(kBlockFlat), 0, s, n, tmp, w.q[1]);
+    e = apply_k(d, w.q[1], tmp, s);  // K s
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pcg_neg, dim3(G), dim3(kBlockFlat), 0, s, n, tmp, w.q[0]);
+    e = apply_k(d, w.r[0], tmp, s);  // K r
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pcg_dots, dim3(G), dim3(kBlockFlat), 0, s, n, w.r[0], tmp, w.d[0], w.q[0],
+                       w.q[1], w.r[1], 0, w.part);
+    hipLaunchKernelGGL(k_pcg_rep_scal, dim3(1), dim3(kBlockFlat), 0, s, w.part, w.part_s + G, G,
+                       w.scal, kPcgReplaceFactor * kPcgReplaceFactor, kGapRestart * kGapRestart);
+    hipLaunchKernelGGL(k_pcg_restart_dirs, dim3(G), dim3(kBlockFlat), 0, s, n, w.scal, w.q[0],
+                       w.q[1], w.r[1]);
     return hipGetLastError();
 }

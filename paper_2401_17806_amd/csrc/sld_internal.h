@@ -108,6 +108,10 @@ struct CgWork {
     bool mx_ok = false;
     bool use_mx = false;
     bool graph_mx[3] = {false, false, false};
+    // pipelined CG (launch_pcg_*): FP64 pressure iterations of the current solve on a mesh of
+    // one tile per block; the FP64 graph was captured with graph_pcg
+    bool use_pcg = false;
+    bool graph_pcg = false;
 };
 
 struct sld_disc_s {
@@ -137,7 +141,7 @@ struct CgScalars {
     // layout of CgWork::scal (doubles)
     enum { RR = 0, BB = 1, TOL2 = 2, ITER = 3, DONE = 4, MAXIT = 5, MEAN = 6, ZERO = 7,
            RTRUE = 8, INTX = 9, ITER0 = 10, ITER1 = 11, IRS = 12, RRNOW = 13, GAP = 14, SIGMA = 15,
-           RTH = 16, TOLU = 17, NSCAL = 18 };
+           RTH = 16, TOLU = 17, PA0 = 18, PA1 = 19, PG0 = 20, PG1 = 21, PLR = 22, NSCAL = 23 };
     // DONE codes written by the iteration kernel
     enum { kConverged = 1, kMaxit = 2, kBreakdown = 3, kRefresh = 4 };
 };
@@ -169,6 +173,23 @@ hipError_t launch_cg_finish(const sld_disc_s* d, double* p_out, double sigma, hi
 hipError_t launch_cg_replace(const sld_disc_s* d, int src, double sigma, hipStream_t s);
 // x += e, e = 0 (FP64 CG, before the solution is read)
 hipError_t launch_cg_fold(const sld_disc_s* d, hipStream_t s);
+// Pipelined CG (kernels_cg.hip): possible when the disc's CG grid has one tile per block; the
+// iteration (replaces launch_cg_step when use_pcg), its setup after launch_cg_setup, and its
+// residual replacement (in place of launch_cg_replace)
+bool pcg_possible(const sld_disc_s* d);
+hipError_t launch_pcg_step(const sld_disc_s* d, int parity, hipStream_t s);
+hipError_t launch_pcg_init(const sld_disc_s* d, hipStream_t s);
+hipError_t launch_pcg_replace(const sld_disc_s* d, hipStream_t s);
+// engine 0 / pipelined 0 of sld_cg_solve: whether FP64 pressure solves on such meshes pipeline
+constexpr bool kAutoPcg = false;
+// Pipelined CG: replacement once the recursive residual has dropped by this factor.  Its
+// recurrences for w, z and s carry rounding errors further than CG's, and the iteration count
+// grows with the distance between replacements: on a walled 24x24x2, p = 3 mesh (rtol 1e-12;
+// CG 2025 iterations) 2953 / 2628 / 2281 iterations at factors 1e-3 / 1e-2 / 1e-1.
+constexpr double kPcgReplaceFactor = 0.1;
+// ... and at least every kPcgSpan iterations (the residual norm can stay high for thousands of
+// iterations while the recurrences drift)
+constexpr int kPcgSpan = 1024;
 // Static CG workspace of sld_cg_solve_static: kStaticCgDoubles doubles (64 MiB) per device, its
 // device address looked up once per device (the device must be current).
 constexpr size_t kStaticCgDoubles = size_t(8) << 20;

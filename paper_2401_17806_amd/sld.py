@@ -37,7 +37,8 @@ _i32 = ctypes.c_int32
 class sld_cg_params(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("maxit", _i32),
                 ("warm_start", _i32), ("graph_block", _i32), ("profile", _i32),
-                ("precision", _i32), ("max_outer", _i32), ("engine", _i32)]
+                ("precision", _i32), ("max_outer", _i32), ("engine", _i32),
+                ("pipelined", _i32)]
 
 
 class sld_cg_report(ctypes.Structure):
@@ -216,17 +217,22 @@ def sld_disc_destroy(h):
 
 
 ENGINES = {"auto": 0, "valu": 1, "mfma": 2}
+PIPELINED = {"auto": 0, "classic": 1, "pipelined": 2}
 
 
 def make_params(rtol=1e-12, maxit=100000, warm_start=False, graph_block=32, profile=False,
-                precision="fp64", inner_rtol=0.5, max_outer=1000, engine="auto"):
+                precision="fp64", inner_rtol=0.5, max_outer=1000, engine="auto",
+                algorithm="auto"):
     if precision not in ("fp64", "mixed"):
         raise ValueError("precision must be 'fp64' or 'mixed'")
     if engine not in ENGINES:
         raise ValueError("engine must be 'auto' (the library's choice), 'valu' or 'mfma'")
+    if algorithm not in PIPELINED:
+        raise ValueError("algorithm must be 'auto' (the library's choice), 'classic' or "
+                         "'pipelined'")
     return sld_cg_params(float(rtol), float(inner_rtol), int(maxit), int(bool(warm_start)),
                          int(graph_block), int(bool(profile)), 1 if precision == "mixed" else 0,
-                         int(max_outer), ENGINES[engine])
+                         int(max_outer), ENGINES[engine], PIPELINED[algorithm])
 
 
 def report_dict(rep, st):
@@ -390,13 +396,14 @@ class Disc:
 
     def sld_cg_solve(self, b, p=None, rtol=1e-12, maxit=100000, warm_start=False,
                      graph_block=32, profile=False, precision="fp64", inner_rtol=0.5,
-                     max_outer=1000, stream=None, engine="auto"):
+                     max_outer=1000, stream=None, engine="auto", algorithm="auto"):
         """Solve K p = b (gauge int p = 0).  precision: "fp64" or "mixed"; engine: "auto" (the
         library's choice), "valu" (vector units) or "mfma" (matrix cores where the mesh has no
-        walls)."""
+        walls); algorithm (FP64 pressure iterations): "auto", "classic" or "pipelined" (meshes of
+        one tile per block of the CG grid)."""
         p = self._new(self.main_shape) if p is None else p
         prm = make_params(rtol, maxit, warm_start, graph_block, profile, precision, inner_rtol,
-                          max_outer, engine)
+                          max_outer, engine, algorithm)
         rep = sld_cg_report()
         st = _lib.sld_cg_solve(self.handle, self._dev(b, self.main_shape, "b"),
                                self._dev(p, self.main_shape, "p"), ctypes.byref(prm),

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(sld.EXPORTED) == set(names)
-    assert sld.sld_abi_version() == 2
+    assert sld.sld_abi_version() == 3
 
 
 @pytest.mark.parametrize("periodic", [True, False])
