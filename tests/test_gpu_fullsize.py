@@ -122,13 +122,16 @@ def test_fullsize_c2_pressure_matches_oracle_sample(torch_dev):
 def test_fullsize_c3_fp64_and_mixed_match_oracle_sample(torch_dev):
     """512x512x2, p = 3 (the bench workload): FP64 and mixed precision, each to a recomputed
     residual of 1e-10, converge, and each pressure equals the oracle's at 1024 sampled DOFs
-    (tests/golden/c3_pressure_sample.txt) to 1e-9 of its max norm; the gauge holds."""
+    (tests/golden/c3_pressure_sample.txt) to 1e-9 of its max norm; the gauge holds.  The FP32
+    process of the mixed form (centred operator inputs, a reliable update at least every 512
+    iterations) needs at most 1.2x the FP64 iterations (measured 1.10x; 1.64x without them)."""
     torch = torch_dev
     _say("[fullsize c3 solves]")
     od, mesh, disc = _setup(512, 3, 3)
     b = _rhs(torch, od, disc, 512, 103)
     sample = _read_sample("c3_pressure_sample.txt")
     w = od.main_weights()
+    iters = {}
     for prec in ("fp64", "mixed"):
         p, rep = disc.sld_cg_solve(b, rtol=1e-10, precision=prec, graph_block=256 if prec == "fp64"
                                    else 64, maxit=200000)
@@ -138,6 +141,8 @@ def test_fullsize_c3_fp64_and_mixed_match_oracle_sample(torch_dev):
         assert err <= 1e-9
         ph = p.cpu().numpy()
         assert abs((w * ph).sum()) <= 1e-12 * np.abs(ph).max() * w.sum()
+        iters[prec] = rep["iters"]
+    assert iters["mixed"] <= 1.2 * iters["fp64"]
 
 
 def test_fullsize_c3_below_the_fp64_floor_is_reported(torch_dev):
