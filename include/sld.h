@@ -211,16 +211,21 @@ typedef struct {
                              reliable updates (refreshes of x and of the true residual), e.g. 0.5 */
     int32_t maxit;        /* iteration cap (mixed: per inner solve) */
     int32_t warm_start;   /* nonzero: p holds the initial guess */
-    int32_t graph_block;  /* iterations per convergence check (even, 2..4096) */
+    int32_t graph_block;  /* iterations per convergence check (even, 2..4096; the mixed form's
+                             FP32 blocks take at most 128, its bound between reliable updates) */
     int32_t profile;      /* nonzero: HIP events on `stream` around each captured block of
                              graph_block iterations; the report gives the mean time per
                              iteration over the blocks whose launches all iterated (FP64 only) */
     int32_t precision;    /* 0: FP64 CG.  1: mixed: one CG process in FP32 (FP32 vectors and
                              operator arithmetic; FP64 geometry and dot products) refreshed by
                              FP64 reliable updates (x accumulated in FP64, residual b - K x
-                             recomputed in FP64; the search direction is kept while the
-                             recursive FP32 residual is within 0.3 of the recomputed one, else
-                             the FP32 process restarts).  Stops at rtol on the FP64 residual,
+                             recomputed in FP64, whenever the FP32 residual has dropped by
+                             inner_rtol and at least every 128 FP32 iterations; the FP32
+                             operator subtracts one DOF value from the inputs of each piece of
+                             K, exact since each piece maps constants to zero, which keeps its
+                             rounding relative to the local variation; the search direction
+                             is kept while the recursive FP32 residual is within 0.3 of the
+                             recomputed one, else the FP32 process restarts).  Stops at rtol on the FP64 residual,
                              or when it no longer improves (rounding floor) */
     int32_t max_outer;    /* mixed only: cap on reliable updates */
     int32_t engine;       /* reference contractions of the pressure iterations: 1 = the vector

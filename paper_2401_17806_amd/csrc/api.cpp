@@ -949,14 +949,20 @@ hipError_t capture_block(sld_disc_s* d, bool fp32, bool shift, int gb, hipGraphE
 #define SLD_REL_GAP_MAX 0.3
 #endif
 // FP32 iterations after which a reliable update is made even if the FP32 residual has not
-// dropped by the refresh factor.  The residual norm of CG on this system is far from monotone
-// (on the 512x512x2, p = 3 solve it first grows twelvefold and stays above its start for about
-// 4000 iterations), and over such a stretch the FP32 recursion drifts: without this bound the
-// first update found a 95% gap and restarted the process, and the mixed solve took 23483 FP32
-// iterations instead of 19491 (FP64 CG: 17765).  An update costs one FP64 residual evaluation,
-// under 0.3% of the iterations between two updates.
+// dropped by the refresh factor (checked after each captured block of iterations).  The
+// residual norm of CG on this system is far from monotone (on the 512x512x2, p = 3 solve it
+// first grows twelvefold and stays above its start for about 4000 iterations), and over such a
+// stretch the FP32 recursion drifts: without this bound the first update found a 95% gap and
+// restarted the process, and the mixed solve took 23483 FP32 iterations instead of 19491 at a
+// bound of 512 (FP64 CG: 17767).  Frequent updates also keep the FP32 recursion close to the
+// FP64 residual later on.  FP32 iterations and ms per mixed solve, p = 3, by bound:
+//   512x512x2: 64: 17760 / 1318, 128: 17660 / 1285, 512: 19073 / 1370
+//   256x256x2: 64:  8822 /  238, 128:  8824 /  233, 512:  9681 /  253
+//   128x128x2: 64:  4906 /   55, 128:  4890 /   53, 512:  4912 /   52
+// and the p = 2 cavity step 140 ms at 64 and 128, 146 ms at 512.  An update costs one FP64
+// residual evaluation and a few flat kernels.
 #ifndef SLD_REL_MAX_SPAN
-#define SLD_REL_MAX_SPAN 512
+#define SLD_REL_MAX_SPAN 128
 #endif
 
 // SLD_CG_TRACE=1 in the environment: each FP64 residual replacement and each reliable update of
@@ -1294,6 +1300,8 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
         // FP32 process restarts from it.
         constexpr double kGapMax = SLD_REL_GAP_MAX;
         constexpr int kMaxSpan = SLD_REL_MAX_SPAN;
+        // the host checks the bound after each captured block: blocks no longer than it
+        const int gb32 = std::max(2, std::min(prm->graph_block, kMaxSpan) & ~1);
         int last_update = 0;
         const double refresh = prm->inner_rtol;
         int total = 0, base = 0;
@@ -1303,7 +1311,7 @@ sld_status cg_solve_impl(sld_disc d_in, const double* b, double* p, const sld_cg
         while (true) {
             IterStats in;
             while (true) {
-                sld_status e = run_block(d, prm->graph_block, s, &in);
+                sld_status e = run_block(d, gb32, s, &in);
                 if (e != SLD_OK) return e;
                 if (in.done || base + in.iters >= prm->maxit) break;
                 // (the block's graph ended with the peek: RRNOW is current)
